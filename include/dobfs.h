@@ -1,0 +1,173 @@
+/*
+ * dobfs.h -- direction-optimized breadth-first search on one AMD Instinct
+ * MI355X (gfx950), whole graph resident in device memory.
+ *
+ * The problem (Section 4, "Methodology"): given an undirected graph stored
+ * as CSR with every undirected edge as two directed entries, and a root,
+ * compute the BFS parent tree and each vertex's depth (hop distance).  The
+ * traversal is level-synchronous (Section 2.2): each level expands the
+ * current frontier either top-down (every frontier vertex claims its
+ * unvisited neighbours, Algorithm 1 top-down branch) or bottom-up (every
+ * unvisited vertex looks for a neighbour in the frontier and stops at the
+ * first, Algorithm 1 bottom-up branch), and a switching rule picks the
+ * direction per level (Section 3.3).
+ *
+ * Conventions for every entry point:
+ *   - Return value: DOBFS_OK (0) or a negative DOBFS_E* status.  Nothing
+ *     throws or aborts across this interface.  dobfs_last_error() gives a
+ *     text for the calling thread's most recent failure (HIP's own text for
+ *     DOBFS_EDEVICE).
+ *   - Vertex IDs are the caller's: int32 in [0, n), n <= 2^31 - 1.  Any
+ *     internal relabelling is undone before results are written.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Output buffers are caller-allocated device memory; the library writes
+ *     them asynchronously on `stream` and they are valid once the stream has
+ *     been synchronised.
+ *   - The library allocates device memory only in dobfs_graph_upload,
+ *     dobfs_pack_upload and the first dobfs_run / dobfs_batch_submit on a
+ *     graph handle (workspaces, reused afterwards).
+ */
+#ifndef DOBFS_H
+#define DOBFS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define DOBFS_OK 0
+#define DOBFS_EINVAL (-1)   /* null pointer, bad size, bad flag, bad CSR       */
+#define DOBFS_ERANGE (-2)   /* a root outside [0, n)                           */
+#define DOBFS_ENOMEM (-3)   /* device allocation failed; nothing leaked        */
+#define DOBFS_EDEVICE (-4)  /* HIP launch or runtime failure                   */
+#define DOBFS_EBUSY (-5)    /* graph still in use (free with runs in flight)   */
+#define DOBFS_ENOTSUP (-6)  /* valid request this build does not support       */
+
+typedef struct dobfs_graph_s* dobfs_graph_t; /* opaque, library-owned */
+
+/* ---- upload flags -------------------------------------------------------- */
+#define DOBFS_SRC_DEVICE 0x1u      /* offsets/indices are device pointers      */
+#define DOBFS_VALIDATE 0x2u        /* check offsets monotone, offsets[0] = 0,
+                                      offsets[n] = m, 0 <= indices < n        */
+#define DOBFS_VALIDATE_SYMMETRY 0x4u /* also check every (u,v) has (v,u);
+                                      rows must then be sorted ascending      */
+#define DOBFS_REINDEX_DEGREE 0x8u  /* relabel internally by degree (highest
+                                      first, ties by ID) and order every
+                                      adjacency list highest-degree neighbour
+                                      first (Section 3.4)                     */
+
+/* ---- direction policies (Section 3.3) ------------------------------------ */
+#define DOBFS_POLICY_EDGE 0      /* top-down -> bottom-up when the next
+                                    frontier's edges times alpha exceed the
+                                    unvisited vertices' edges; back when the
+                                    frontier shrinks below n / beta          */
+#define DOBFS_POLICY_PAPER 1     /* top-down -> bottom-up when paper_pct% of
+                                    the frontier's edges (the estimated next
+                                    frontier) exceeds n / paper_div; back to
+                                    top-down after paper_bu_steps bottom-up
+                                    levels, for the rest of the traversal    */
+#define DOBFS_POLICY_FORCED_TD 2 /* every level top-down                      */
+#define DOBFS_POLICY_FORCED_BU 3 /* every level bottom-up                     */
+#define DOBFS_POLICY_RANDOM 4    /* direction of level L = bit of a hash of
+                                    (seed, L); for testing invariance        */
+
+typedef struct {
+  int32_t policy;          /* DOBFS_POLICY_*                                */
+  int32_t alpha;           /* EDGE, default 14                              */
+  int32_t beta;            /* EDGE, default 24                              */
+  int32_t paper_pct;       /* PAPER, default 10                             */
+  int32_t paper_div;       /* PAPER, default 64                             */
+  int32_t paper_bu_steps;  /* PAPER, default 3                              */
+  int32_t td_wave_cut;     /* top-down: degree above which a whole wavefront
+                              works on one vertex (default 16)              */
+  int32_t td_huge_cut;     /* top-down: degree above which a vertex's edges
+                              are split over many wavefronts (default 4096) */
+  int32_t bu_heavy_cut;    /* bottom-up: degree above which a wavefront scans
+                              one vertex cooperatively (default 256)        */
+  int32_t chunk_levels;    /* levels enqueued per host check (default 8)    */
+  uint64_t seed;           /* RANDOM policy                                 */
+} dobfs_params;
+
+/* One record per level, written on the device without host involvement. */
+typedef struct {
+  int32_t level;           /* L: the frontier holds the vertices of depth L */
+  int32_t dir;             /* 0 top-down, 1 bottom-up                        */
+  int64_t n_f;             /* frontier vertices                              */
+  int64_t m_f;             /* summed degree of the frontier                  */
+  int64_t m_u;             /* summed degree of unvisited vertices before L   */
+  int64_t scanned;         /* bottom-up: unvisited vertices examined         */
+  int64_t checked;         /* edges examined (bottom-up: up to first hit)    */
+  int64_t found;           /* vertices of depth L+1                          */
+  int64_t found_deg;       /* their summed degree                            */
+  uint64_t t_end;          /* device wall clock (100 MHz) at level end       */
+} dobfs_level_rec;
+
+typedef struct {
+  int32_t levels;          /* levels expanded (deepest depth + 1)           */
+  int32_t log_len;         /* records written to `log` (<= log_cap)         */
+  int64_t reached;         /* vertices with depth >= 0                       */
+  int64_t m_c;             /* undirected edges in the root's component:
+                              half the summed degree of reached vertices   */
+  int64_t checked;         /* edges examined, all levels                     */
+  uint64_t t_begin;        /* device wall clock at init                      */
+  dobfs_level_rec* log;    /* caller's host array, or NULL                   */
+  int32_t log_cap;         /* its capacity in records                        */
+  int32_t reserved;
+} dobfs_stats;
+
+typedef struct {
+  int64_t n, m;            /* vertices, directed CSR entries                 */
+  int64_t n_nonisolated;   /* vertices of degree >= 1                        */
+  int64_t max_degree;
+  int64_t device_bytes;    /* graph arrays resident on the device            */
+  uint32_t flags;          /* upload flags kept (DOBFS_REINDEX_DEGREE)       */
+  int32_t reserved;
+} dobfs_graph_info_t;
+
+/* Fills `p` with the defaults listed above. */
+void dobfs_default_params(dobfs_params* p);
+
+/* Makes the graph resident on the current device.
+   offsets: int64[n+1], indices: int32[m], host memory unless
+   DOBFS_SRC_DEVICE; the CSR must be symmetric (bottom-up steps read the
+   reverse edges) and free of self-loops; rows need not be sorted unless
+   DOBFS_VALIDATE_SYMMETRY is given.  The arrays are copied: the caller may
+   free them when the call returns.  The call is synchronous.
+   Errors: EINVAL (null pointers, n < 1, n > 2^31-1, m < 0, unknown flag,
+   validation failure), ENOMEM, EDEVICE. */
+int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n, int64_t m,
+                       uint32_t flags, void* stream, dobfs_graph_t* out);
+
+/* Releases a graph and its workspaces after waiting for its runs to end.
+   NULL is accepted.  Errors: EDEVICE. */
+int dobfs_graph_free(dobfs_graph_t g);
+
+int dobfs_graph_info(dobfs_graph_t g, dobfs_graph_info_t* info);
+
+/* Single-source direction-optimized BFS from `root`.
+   depth:  device int32[n], out: hop distance from root, -1 if unreachable.
+   parent: device int32[n] or NULL, out: a neighbour one level closer to the
+           root (root: itself; unreachable: -1).  Any such neighbour is a
+           correct answer; which one is picked may vary between runs.
+   p:      NULL for defaults.
+   stats:  NULL, or filled before return (the call then waits for the
+           stream to finish the traversal).
+   The level loop runs on the device; the host only checks, once per
+   `chunk_levels` levels, whether the traversal has ended, so the call
+   returns once the last level is known to be enqueued.
+   Errors: EINVAL, ERANGE (root), ENOMEM (first-run workspace), EDEVICE. */
+int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, const dobfs_params* p,
+              dobfs_stats* stats, void* stream);
+
+/* Strings for a status; valid forever. */
+const char* dobfs_strerror(int status);
+/* Text of the calling thread's most recent failure ("" if none). */
+const char* dobfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOBFS_H */

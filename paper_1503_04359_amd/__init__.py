@@ -1,0 +1,221 @@
+"""Direction-optimized breadth-first search on one MI355X (gfx950).
+
+Thin Python binding over the C ABI declared in ``include/dobfs.h`` and built
+into ``libdobfs.so``: argument marshalling only.  Every step of a traversal
+runs in the library's HIP kernels; PyTorch supplies device memory and
+streams.  There is no fallback: importing this package fails when the HIP
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdobfs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it first (python __graft_entry__.py build, "
+        "or python paper_1503_04359_amd/_build.py)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- status codes and flags (include/dobfs.h) ------------------------------
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+SRC_DEVICE, VALIDATE, VALIDATE_SYMMETRY, REINDEX_DEGREE = 0x1, 0x2, 0x4, 0x8
+POLICY_EDGE, POLICY_PAPER, POLICY_FORCED_TD, POLICY_FORCED_BU, POLICY_RANDOM = 0, 1, 2, 3, 4
+POLICIES = {"edge": POLICY_EDGE, "paper": POLICY_PAPER, "td": POLICY_FORCED_TD,
+            "bu": POLICY_FORCED_BU, "random": POLICY_RANDOM}
+
+EXPORTED = ("dobfs_default_params", "dobfs_graph_upload", "dobfs_graph_free", "dobfs_graph_info",
+            "dobfs_run", "dobfs_strerror", "dobfs_last_error")
+
+
+class DobfsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.dobfs_strerror(status).decode()
+        detail = _lib.dobfs_last_error().decode()
+        super().__init__(f"{where}: {msg}" + (f" ({detail})" if detail else ""))
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int32), ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32),
+                ("paper_pct", ctypes.c_int32), ("paper_div", ctypes.c_int32),
+                ("paper_bu_steps", ctypes.c_int32), ("td_wave_cut", ctypes.c_int32),
+                ("td_huge_cut", ctypes.c_int32), ("bu_heavy_cut", ctypes.c_int32),
+                ("chunk_levels", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class LevelRec(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("dir", ctypes.c_int32), ("n_f", ctypes.c_int64),
+                ("m_f", ctypes.c_int64), ("m_u", ctypes.c_int64), ("scanned", ctypes.c_int64),
+                ("checked", ctypes.c_int64), ("found", ctypes.c_int64), ("found_deg", ctypes.c_int64),
+                ("t_end", ctypes.c_uint64)]
+
+
+class CStats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("log_len", ctypes.c_int32), ("reached", ctypes.c_int64),
+                ("m_c", ctypes.c_int64), ("checked", ctypes.c_int64), ("t_begin", ctypes.c_uint64),
+                ("log", ctypes.POINTER(LevelRec)), ("log_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class CGraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("n_nonisolated", ctypes.c_int64),
+                ("max_degree", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+_vp, _i64 = ctypes.c_void_p, ctypes.c_int64
+_lib.dobfs_default_params.restype = None
+_lib.dobfs_default_params.argtypes = [ctypes.POINTER(CParams)]
+_lib.dobfs_graph_upload.restype = ctypes.c_int
+_lib.dobfs_graph_upload.argtypes = [_vp, _vp, _i64, _i64, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)]
+_lib.dobfs_graph_free.restype = ctypes.c_int
+_lib.dobfs_graph_free.argtypes = [_vp]
+_lib.dobfs_graph_info.restype = ctypes.c_int
+_lib.dobfs_graph_info.argtypes = [_vp, ctypes.POINTER(CGraphInfo)]
+_lib.dobfs_run.restype = ctypes.c_int
+_lib.dobfs_run.argtypes = [_vp, _i64, _vp, _vp, ctypes.POINTER(CParams), ctypes.POINTER(CStats), _vp]
+_lib.dobfs_strerror.restype = ctypes.c_char_p
+_lib.dobfs_strerror.argtypes = [ctypes.c_int]
+_lib.dobfs_last_error.restype = ctypes.c_char_p
+_lib.dobfs_last_error.argtypes = []
+
+
+def _check(status: int, where: str) -> None:
+    if status != OK:
+        raise DobfsError(status, where)
+
+
+def default_params() -> CParams:
+    p = CParams()
+    _lib.dobfs_default_params(ctypes.byref(p))
+    return p
+
+
+def make_params(policy: str | int = "edge", **kw) -> CParams:
+    p = default_params()
+    p.policy = POLICIES[policy] if isinstance(policy, str) else int(policy)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, int(v))
+    return p
+
+
+@dataclass
+class Stats:
+    levels: int
+    reached: int
+    m_c: int
+    checked: int
+    log: list = field(default_factory=list)
+
+    def dirs(self) -> list[int]:
+        return [r["dir"] for r in self.log]
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(int(t.data_ptr()))
+
+
+class Graph:
+    """A graph resident on the current device."""
+
+    def __init__(self, handle: ctypes.c_void_p, n: int, m: int):
+        self._h = handle
+        self.n = n
+        self.m = m
+
+    @classmethod
+    def upload(cls, offsets, indices, *, reindex: bool = False, check_symmetry: bool = False,
+               stream=None) -> "Graph":
+        """offsets int64[n+1], indices int32[m]: numpy arrays (host) or torch
+        tensors on the GPU (copied on the device)."""
+        import torch
+        flags = VALIDATE | (VALIDATE_SYMMETRY if check_symmetry else 0) | (REINDEX_DEGREE if reindex else 0)
+        if isinstance(offsets, torch.Tensor):
+            if offsets.dtype != torch.int64 or indices.dtype != torch.int32:
+                raise TypeError("offsets must be int64 and indices int32")
+            if not (offsets.is_cuda and indices.is_cuda):
+                offsets, indices = offsets.numpy(), indices.numpy()
+            else:
+                offsets, indices = offsets.contiguous(), indices.contiguous()
+                flags |= SRC_DEVICE
+                n, m = offsets.shape[0] - 1, indices.shape[0]
+                h = ctypes.c_void_p()
+                _check(_lib.dobfs_graph_upload(_ptr(offsets), _ptr(indices), n, m, flags, _stream_ptr(stream),
+                                               ctypes.byref(h)), "dobfs_graph_upload")
+                return cls(h, n, m)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        idx = np.ascontiguousarray(indices, dtype=np.int32)
+        n, m = off.shape[0] - 1, idx.shape[0]
+        h = ctypes.c_void_p()
+        _check(_lib.dobfs_graph_upload(off.ctypes.data, idx.ctypes.data if m else None, n, m, flags,
+                                       _stream_ptr(stream), ctypes.byref(h)), "dobfs_graph_upload")
+        return cls(h, n, m)
+
+    def info(self) -> dict:
+        i = CGraphInfo()
+        _check(_lib.dobfs_graph_info(self._h, ctypes.byref(i)), "dobfs_graph_info")
+        return {k: getattr(i, k) for k, _ in CGraphInfo._fields_ if k != "reserved"}
+
+    def run(self, root: int, depth=None, parent=None, params: CParams | None = None, stats: bool = False,
+            stream=None, want_parent: bool = True, log_cap: int = 4096):
+        """Single-source traversal.  Returns (depth, parent, Stats|None);
+        depth/parent are int32 CUDA tensors valid after the stream syncs."""
+        import torch
+        if depth is None:
+            depth = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        if parent is None and want_parent:
+            parent = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        for t in (depth, parent):
+            if t is not None and (t.dtype != torch.int32 or t.numel() < self.n or not t.is_cuda
+                                  or not t.is_contiguous()):
+                raise ValueError("depth/parent must be contiguous int32 CUDA tensors of length n")
+        cs = None
+        log = None
+        if stats:
+            log = (LevelRec * log_cap)()
+            cs = CStats()
+            cs.log = ctypes.cast(log, ctypes.POINTER(LevelRec))
+            cs.log_cap = log_cap
+        st = _lib.dobfs_run(self._h, int(root), _ptr(depth), _ptr(parent) if parent is not None else None,
+                            ctypes.byref(params) if params is not None else None,
+                            ctypes.byref(cs) if cs is not None else None, _stream_ptr(stream))
+        _check(st, "dobfs_run")
+        out_stats = None
+        if stats:
+            recs = [{k: getattr(log[i], k) for k, _ in LevelRec._fields_} for i in range(cs.log_len)]
+            out_stats = Stats(cs.levels, cs.reached, cs.m_c, cs.checked, recs)
+        return depth, parent, out_stats
+
+    def free(self) -> None:
+        if self._h:
+            _check(_lib.dobfs_graph_free(self._h), "dobfs_graph_free")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()

@@ -1,0 +1,118 @@
+/*
+ * Internal declarations of the direction-optimized BFS library.
+ *
+ * Device-memory layout of one resident graph (all device arrays):
+ *   off      int64[n+1]   CSR row offsets (both directions of every edge)
+ *   idx      int32[m]     neighbour IDs, each row in the order bottom-up
+ *                         steps scan it
+ *   iso      uint64[W]    W = ceil(n/64) words; bit v set when deg(v) = 0 or
+ *                         v >= n.  It is the visited bitmap's initial state:
+ *                         such vertices can never be reached through an edge,
+ *                         so marking them visited lets bottom-up steps skip
+ *                         them without reading their offsets.
+ *   new2old / old2new int32[n]   only for degree-relabelled graphs.
+ *
+ * Workspace of one traversal (reused by later traversals of the graph):
+ *   vis      uint64[W]    visited set (bit per vertex)
+ *   fr[2]    uint64[W]    frontier bitmaps of levels L (even/odd)
+ *   q[2]     int32[n]     frontier queues for top-down levels
+ *   huge_u / huge_base    top-down vertices whose edges are split across
+ *                         wavefronts, with the first chunk index of each
+ *   ctl                   level state and counters (below)
+ *   log                   one dobfs_level_rec per level
+ */
+#ifndef DOBFS_INTERNAL_H
+#define DOBFS_INTERNAL_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dobfs.h"
+
+namespace dobfs {
+
+constexpr int kBlock = 256;          /* threads per workgroup (4 wavefronts) */
+constexpr int kWave = 64;
+constexpr int kHugeChunk = 2048;     /* edges per wavefront task for split vertices */
+constexpr int kMinHugeCut = 256;     /* lower bound of td_huge_cut */
+constexpr int kDirTD = 0;
+constexpr int kDirBU = 1;
+constexpr int kAuxNone = 0;
+constexpr int kAuxHuge = 1;          /* split top-down vertices still to expand */
+constexpr int kAuxToQueue = 2;       /* bottom-up -> top-down: bitmap to queue */
+
+/* Level state, advanced on the device by the last workgroup of each level. */
+struct Ctl {
+  int32_t level;        /* L: frontier = vertices of depth L              */
+  int32_t dir;          /* direction of level L                           */
+  int32_t done;         /* set when a level finds no new vertex           */
+  int32_t qsel;         /* q[qsel] holds the level-L queue (top-down)     */
+  int32_t aux;          /* kAux*: work for the aux kernel of this level   */
+  int32_t bu_run;       /* consecutive bottom-up levels just completed    */
+  int32_t bu_phases;    /* bottom-up phases started so far                */
+  int32_t levels;       /* final level count                              */
+  int32_t log_len;
+  int32_t pad0;
+  int64_t n_f, m_f, m_u;
+  /* accumulators of the level in progress */
+  int64_t nf_next;      /* also the top-down queue append cursor          */
+  int64_t mf_next;
+  int64_t checked;
+  int64_t scanned;
+  unsigned long long huge_pack; /* (entries << 32) | chunks               */
+  int64_t q_fill;       /* bitmap->queue append cursor                    */
+  uint32_t ticket;      /* workgroups finished in the current kernel      */
+  uint32_t pad1;
+  /* totals */
+  int64_t reached, reached_deg, checked_total;
+  uint64_t t_begin;
+};
+
+struct KParams {
+  int32_t policy, alpha, beta, paper_pct, paper_div, paper_bu_steps;
+  int32_t td_wave_cut, td_huge_cut, bu_heavy_cut;
+  int32_t pad;
+  uint64_t seed;
+};
+
+struct GView {
+  const int64_t* off;
+  const int32_t* idx;
+  const uint64_t* iso;
+  int64_t n, m;
+  int64_t words;         /* ceil(n/64)                                     */
+  int64_t words_active;  /* words that may hold an unvisited vertex        */
+};
+
+struct WView {
+  uint64_t* vis;
+  uint64_t* fr0;
+  uint64_t* fr1;
+  int32_t* q0;
+  int32_t* q1;
+  int32_t* huge_u;
+  uint32_t* huge_base;
+  int32_t* depth;
+  int32_t* parent;
+  Ctl* ctl;
+  dobfs_level_rec* log;
+  int32_t log_cap;
+  int32_t pad;
+};
+
+/* Kernel launchers (bfs_kernels.hip). */
+hipError_t launch_init(const GView& g, const WView& w, int64_t root, int32_t first_dir, int grid,
+                       hipStream_t s);
+hipError_t launch_level(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s);
+hipError_t launch_aux(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s);
+hipError_t level_grid(int* grid);
+
+/* Graph preparation launchers (graph_kernels.hip). */
+hipError_t launch_graph_scan(const int64_t* off, int64_t n, uint64_t* iso, int64_t* counters,
+                             int grid, hipStream_t s);
+hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int symmetry,
+                           int32_t* bad, int grid, hipStream_t s);
+
+}  // namespace dobfs
+
+#endif

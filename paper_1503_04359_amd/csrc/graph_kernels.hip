@@ -1,0 +1,105 @@
+/*
+ * Graph preparation kernels: degree summary and CSR validation.
+ */
+#include <hip/hip_runtime.h>
+
+#include "dobfs_internal.h"
+
+namespace dobfs {
+namespace {
+
+__device__ __forceinline__ int lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
+}
+
+/* iso[w] bit i = (vertex 64w+i has degree 0 or lies beyond n).
+   counters[0] += vertices of degree >= 1, counters[1] = max degree,
+   counters[2] += vertices of degree > kMinHugeCut. */
+__global__ void __launch_bounds__(kBlock) k_graph_scan(const int64_t* off, int64_t n, uint64_t* iso,
+                                                     int64_t* counters) {
+  const int lane = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int64_t words = (n + 63) / 64;
+  int64_t nonisolated = 0, maxdeg = 0, huge = 0;
+  for (int64_t wd = wave; wd < words; wd += nwaves) {
+    const int64_t v = wd * kWave + lane;
+    int64_t deg = 0;
+    if (v < n) deg = off[v + 1] - off[v];
+    const uint64_t empty = __ballot(deg == 0);
+    if (lane == 0) iso[wd] = empty;
+    nonisolated += deg > 0;
+    huge += deg > kMinHugeCut;
+    maxdeg = deg > maxdeg ? deg : maxdeg;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    nonisolated += __shfl_xor(nonisolated, o);
+    huge += __shfl_xor(huge, o);
+    const int64_t y = __shfl_xor(maxdeg, o);
+    maxdeg = y > maxdeg ? y : maxdeg;
+  }
+  if (lane == 0) {
+    if (nonisolated) atomicAdd(reinterpret_cast<unsigned long long*>(&counters[0]), (unsigned long long)nonisolated);
+    atomicMax(reinterpret_cast<unsigned long long*>(&counters[1]), (unsigned long long)maxdeg);
+    if (huge) atomicAdd(reinterpret_cast<unsigned long long*>(&counters[2]), (unsigned long long)huge);
+  }
+}
+
+/* bad[0]: first problem found (0 none, 1 offsets, 2 index range,
+   3 self-loop, 4 missing reverse edge). */
+__global__ void __launch_bounds__(kBlock) k_validate(const int64_t* off, const int32_t* idx, int64_t n,
+                                                   int64_t m, int symmetry, int32_t* bad) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  if (tid == 0 && (off[0] != 0 || off[n] != m)) atomicCAS(bad, 0, 1);
+  for (int64_t v = tid; v < n; v += nth) {
+    const int64_t b = off[v], e = off[v + 1];
+    if (b > e || b < 0 || e > m) {
+      atomicCAS(bad, 0, 1);
+      continue;
+    }
+    for (int64_t k = b; k < e; ++k) {
+      const int32_t u = idx[k];
+      if (u < 0 || (int64_t)u >= n) {
+        atomicCAS(bad, 0, 2);
+        break;
+      }
+      if ((int64_t)u == v) {
+        atomicCAS(bad, 0, 3);
+        break;
+      }
+      if (symmetry) {
+        int64_t lo = off[u], hi = off[u + 1];
+        bool ok = false;
+        if (lo >= 0 && hi <= m && lo <= hi) {
+          while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            const int32_t x = idx[mid];
+            if (x == (int32_t)v) { ok = true; break; }
+            if (x < (int32_t)v) lo = mid + 1; else hi = mid;
+          }
+        }
+        if (!ok) {
+          atomicCAS(bad, 0, 4);
+          break;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_graph_scan(const int64_t* off, int64_t n, uint64_t* iso, int64_t* counters, int grid,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_graph_scan, dim3(grid), dim3(kBlock), 0, s, off, n, iso, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int symmetry,
+                           int32_t* bad, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3(grid), dim3(kBlock), 0, s, off, idx, n, m, symmetry, bad);
+  return hipGetLastError();
+}
+
+}  // namespace dobfs
