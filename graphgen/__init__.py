@@ -75,6 +75,9 @@ def _load():
     lib.gg_rmat_thresholds.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
     lib.gg_set_threads.restype = None
     lib.gg_set_threads.argtypes = [ctypes.c_int]
+    lib.gg_root_candidates.restype = None
+    lib.gg_root_candidates.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_void_p]
     lib.gg_chung_lu_weights.restype = ctypes.c_int
     lib.gg_chung_lu_weights.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                         P(ctypes.c_double), P(ctypes.c_double)]
@@ -257,3 +260,118 @@ def disjoint_union(*gs: CSR) -> CSR:
         dsts.append(g.indices.astype(np.int64) + base)
         base += g.n
     return from_edges(base, np.concatenate(srcs), np.concatenate(dsts), "union")
+
+
+# ---------------------------------------------------------------------------
+# Device builder (graphs too large for the host builder).
+
+_dlib = None
+_DLIB_PATH = os.path.join(_HERE, "libgraphgen_gpu.so")
+
+
+def _load_device():
+    global _dlib
+    if _dlib is not None:
+        return _dlib
+    if not os.path.exists(_DLIB_PATH):
+        raise ImportError(f"{_DLIB_PATH} is missing: build it first (python graphgen/_build.py)")
+    lib = ctypes.CDLL(_DLIB_PATH)
+    P = ctypes.POINTER
+    lib.ggd_kronecker.restype = ctypes.c_int
+    lib.ggd_kronecker.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int,
+                                  P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_int64), P(ctypes.c_int64),
+                                  ctypes.c_void_p]
+    lib.ggd_free.restype = None
+    lib.ggd_free.argtypes = [ctypes.c_void_p]
+    lib.ggd_last_error.restype = ctypes.c_char_p
+    lib.ggd_last_error.argtypes = []
+    _dlib = lib
+    return lib
+
+
+class _CudaArray:
+    """Exposes a raw device allocation to torch through the CUDA array
+    interface (no copy)."""
+
+    def __init__(self, ptr: int, n: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False),
+                                         "version": 2, "strides": None}
+
+
+class DeviceCSR:
+    """Symmetric CSR resident on the current GPU, owned by this object
+    (released by :meth:`free`).  ``offsets_ptr``/``indices_ptr`` are raw
+    device addresses of int64[n+1] / int32[m]."""
+
+    def __init__(self, off_ptr: int, idx_ptr: int, n: int, m: int, name: str):
+        self.offsets_ptr = off_ptr
+        self.indices_ptr = idx_ptr
+        self.n = n
+        self.m = m
+        self.name = name
+
+    def offsets_tensor(self):
+        import torch
+        return torch.as_tensor(_CudaArray(self.offsets_ptr, self.n + 1, "<i8"), device="cuda")
+
+    def indices_tensor(self):
+        import torch
+        return torch.as_tensor(_CudaArray(self.indices_ptr, max(self.m, 1), "<i4"), device="cuda")[: self.m]
+
+    def to_host(self) -> CSR:
+        return CSR(self.offsets_tensor().cpu().numpy(), self.indices_tensor().cpu().numpy(), self.name)
+
+    def degree_of(self, vertices: np.ndarray) -> np.ndarray:
+        import torch
+        off = self.offsets_tensor()
+        v = torch.as_tensor(np.asarray(vertices, dtype=np.int64), device="cuda")
+        return (off[v + 1] - off[v]).cpu().numpy()
+
+    def free(self) -> None:
+        if self.offsets_ptr:
+            _load_device().ggd_free(ctypes.c_void_p(self.offsets_ptr))
+            _load_device().ggd_free(ctypes.c_void_p(self.indices_ptr))
+            self.offsets_ptr = self.indices_ptr = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def kronecker_device(scale: int, edgefactor: int = KRON_EDGEFACTOR, seed: int = 1, a: float = KRON_A,
+                     b: float = KRON_B, c: float = KRON_C, permute: bool = True, stream=None) -> DeviceCSR:
+    """Same graph as :func:`kronecker`, built on the current GPU."""
+    import torch
+    lib = _load_device()
+    thr = (ctypes.c_uint32 * 3)(*rmat_thresholds(a, b, c))
+    off, idx = ctypes.c_void_p(), ctypes.c_void_p()
+    n, m = ctypes.c_int64(0), ctypes.c_int64(0)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib.ggd_kronecker(int(scale), int(edgefactor), int(seed), ctypes.addressof(thr), 1 if permute else 0,
+                           ctypes.byref(off), ctypes.byref(idx), ctypes.byref(n), ctypes.byref(m),
+                           ctypes.c_void_p(int(s.cuda_stream)))
+    if rc:
+        raise RuntimeError(f"graphgen device builder failed ({rc}): {lib.ggd_last_error().decode()}")
+    return DeviceCSR(off.value, idx.value, n.value, m.value, f"kron-s{scale}-ef{edgefactor}-seed{seed}")
+
+
+def sample_roots_device(g: DeviceCSR, count: int, seed: int) -> np.ndarray:
+    """Same roots as :func:`sample_roots` would draw for this graph."""
+    lib = _load()
+    out: list[int] = []
+    first, batch = 0, max(64, 4 * count)
+    while len(out) < count:
+        if first > 64 * g.n + 4096:
+            raise ValueError("not enough roots of degree >= 1")
+        cand = np.empty(batch, dtype=np.int64)
+        lib.gg_root_candidates(g.n, int(seed), first, batch, cand.ctypes.data)
+        deg = g.degree_of(cand)
+        for c_, d_ in zip(cand.tolist(), deg.tolist()):
+            if d_ >= 1 and c_ not in out:
+                out.append(c_)
+                if len(out) == count:
+                    break
+        first += batch
+    return np.array(out, dtype=np.int64)

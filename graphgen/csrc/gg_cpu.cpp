@@ -398,6 +398,13 @@ void gg_csr_free(gg_csr* g) {
   delete g;
 }
 
+/* The candidate sequence behind gg_sample_roots: out[i] = candidate number
+   first+i, uniform in [0, n). */
+void gg_root_candidates(int64_t n, uint64_t seed, int64_t first, int64_t count, int64_t* out) {
+  const uint64_t key = gg_stream_key(seed, GG_STREAM_ROOTS);
+  for (int64_t i = 0; i < count; ++i) out[i] = (int64_t)gg_below(gg_draw(key, (uint64_t)(first + i)), (uint64_t)n);
+}
+
 /* `count` distinct roots, uniform over the vertices of degree >= 1, drawn in
    order from the ROOTS stream of `seed`.  Returns the number found. */
 int64_t gg_sample_roots(const int64_t* offsets, int64_t n, uint64_t seed, int64_t count, int64_t* out) {

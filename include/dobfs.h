@@ -57,6 +57,15 @@ typedef struct dobfs_graph_s* dobfs_graph_t; /* opaque, library-owned */
                                       first, ties by ID) and order every
                                       adjacency list highest-degree neighbour
                                       first (Section 3.4)                     */
+#define DOBFS_BORROW 0x10u         /* with DOBFS_SRC_DEVICE: use the caller's
+                                      arrays in place, no copy; the caller
+                                      keeps them alive and unchanged until
+                                      dobfs_graph_free                        */
+
+/* ---- run flags (dobfs_params.flags) --------------------------------------- */
+#define DOBFS_RUN_TIME_KERNELS 0x1u /* bracket every level-kernel launch with
+                                      HIP events on `stream`; the durations
+                                      are reported in dobfs_stats            */
 
 /* ---- direction policies (Section 3.3) ------------------------------------ */
 #define DOBFS_POLICY_EDGE 0      /* top-down -> bottom-up when the next
@@ -87,6 +96,7 @@ typedef struct {
   int32_t bu_heavy_cut;    /* bottom-up: degree above which a wavefront scans
                               one vertex cooperatively (default 256)        */
   int32_t chunk_levels;    /* levels enqueued per host check (default 8)    */
+  uint32_t flags;          /* DOBFS_RUN_* (default 0)                       */
   uint64_t seed;           /* RANDOM policy                                 */
 } dobfs_params;
 
@@ -102,6 +112,8 @@ typedef struct {
   int64_t found;           /* vertices of depth L+1                          */
   int64_t found_deg;       /* their summed degree                            */
   uint64_t t_end;          /* device wall clock (100 MHz) at level end       */
+  float kernel_ms;         /* level-kernel duration (DOBFS_RUN_TIME_KERNELS) */
+  int32_t reserved;
 } dobfs_level_rec;
 
 typedef struct {
@@ -114,7 +126,10 @@ typedef struct {
   uint64_t t_begin;        /* device wall clock at init                      */
   dobfs_level_rec* log;    /* caller's host array, or NULL                   */
   int32_t log_cap;         /* its capacity in records                        */
-  int32_t reserved;
+  int32_t level_launches;  /* level-kernel launches, including those that
+                              found the traversal finished and returned     */
+  double level_kernel_ms;  /* summed duration of those launches
+                              (DOBFS_RUN_TIME_KERNELS, else 0)              */
 } dobfs_stats;
 
 typedef struct {
@@ -131,10 +146,12 @@ void dobfs_default_params(dobfs_params* p);
 
 /* Makes the graph resident on the current device.
    offsets: int64[n+1], indices: int32[m], host memory unless
-   DOBFS_SRC_DEVICE; the CSR must be symmetric (bottom-up steps read the
+   DOBFS_SRC_DEVICE (then copied on the device, or adopted without a copy
+   with DOBFS_BORROW); the CSR must be symmetric (bottom-up steps read the
    reverse edges) and free of self-loops; rows need not be sorted unless
-   DOBFS_VALIDATE_SYMMETRY is given.  The arrays are copied: the caller may
-   free them when the call returns.  The call is synchronous.
+   DOBFS_VALIDATE_SYMMETRY is given.  Unless borrowed, the arrays are
+   copied and the caller may free them when the call returns.  Offsets and
+   neighbour IDs are always range-checked.  The call is synchronous.
    Errors: EINVAL (null pointers, n < 1, n > 2^31-1, m < 0, unknown flag,
    validation failure), ENOMEM, EDEVICE. */
 int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n, int64_t m,

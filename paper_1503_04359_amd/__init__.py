@@ -26,7 +26,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- status codes and flags (include/dobfs.h) ------------------------------
 OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
-SRC_DEVICE, VALIDATE, VALIDATE_SYMMETRY, REINDEX_DEGREE = 0x1, 0x2, 0x4, 0x8
+SRC_DEVICE, VALIDATE, VALIDATE_SYMMETRY, REINDEX_DEGREE, BORROW = 0x1, 0x2, 0x4, 0x8, 0x10
+RUN_TIME_KERNELS = 0x1
 POLICY_EDGE, POLICY_PAPER, POLICY_FORCED_TD, POLICY_FORCED_BU, POLICY_RANDOM = 0, 1, 2, 3, 4
 POLICIES = {"edge": POLICY_EDGE, "paper": POLICY_PAPER, "td": POLICY_FORCED_TD,
             "bu": POLICY_FORCED_BU, "random": POLICY_RANDOM}
@@ -48,21 +49,21 @@ class CParams(ctypes.Structure):
                 ("paper_pct", ctypes.c_int32), ("paper_div", ctypes.c_int32),
                 ("paper_bu_steps", ctypes.c_int32), ("td_wave_cut", ctypes.c_int32),
                 ("td_huge_cut", ctypes.c_int32), ("bu_heavy_cut", ctypes.c_int32),
-                ("chunk_levels", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("chunk_levels", ctypes.c_int32), ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
 
 
 class LevelRec(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int32), ("dir", ctypes.c_int32), ("n_f", ctypes.c_int64),
                 ("m_f", ctypes.c_int64), ("m_u", ctypes.c_int64), ("scanned", ctypes.c_int64),
                 ("checked", ctypes.c_int64), ("found", ctypes.c_int64), ("found_deg", ctypes.c_int64),
-                ("t_end", ctypes.c_uint64)]
+                ("t_end", ctypes.c_uint64), ("kernel_ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
 
 
 class CStats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("log_len", ctypes.c_int32), ("reached", ctypes.c_int64),
                 ("m_c", ctypes.c_int64), ("checked", ctypes.c_int64), ("t_begin", ctypes.c_uint64),
                 ("log", ctypes.POINTER(LevelRec)), ("log_cap", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("level_launches", ctypes.c_int32), ("level_kernel_ms", ctypes.c_double)]
 
 
 class CGraphInfo(ctypes.Structure):
@@ -116,6 +117,8 @@ class Stats:
     m_c: int
     checked: int
     log: list = field(default_factory=list)
+    level_launches: int = 0
+    level_kernel_ms: float = 0.0
 
     def dirs(self) -> list[int]:
         return [r["dir"] for r in self.log]
@@ -139,6 +142,19 @@ class Graph:
         self._h = handle
         self.n = n
         self.m = m
+
+    @classmethod
+    def from_device_pointers(cls, offsets_ptr: int, indices_ptr: int, n: int, m: int, *, borrow: bool = True,
+                             reindex: bool = False, check_symmetry: bool = False, stream=None) -> "Graph":
+        """CSR already on the device as raw pointers (int64[n+1], int32[m]).
+        With ``borrow`` the arrays are used in place and must outlive the
+        graph."""
+        flags = SRC_DEVICE | VALIDATE | (BORROW if borrow else 0)
+        flags |= (VALIDATE_SYMMETRY if check_symmetry else 0) | (REINDEX_DEGREE if reindex else 0)
+        h = ctypes.c_void_p()
+        _check(_lib.dobfs_graph_upload(ctypes.c_void_p(offsets_ptr), ctypes.c_void_p(indices_ptr), int(n), int(m),
+                                       flags, _stream_ptr(stream), ctypes.byref(h)), "dobfs_graph_upload")
+        return cls(h, int(n), int(m))
 
     @classmethod
     def upload(cls, offsets, indices, *, reindex: bool = False, check_symmetry: bool = False,
@@ -200,7 +216,8 @@ class Graph:
         out_stats = None
         if stats:
             recs = [{k: getattr(log[i], k) for k, _ in LevelRec._fields_} for i in range(cs.log_len)]
-            out_stats = Stats(cs.levels, cs.reached, cs.m_c, cs.checked, recs)
+            out_stats = Stats(cs.levels, cs.reached, cs.m_c, cs.checked, recs, cs.level_launches,
+                              cs.level_kernel_ms)
         return depth, parent, out_stats
 
     def free(self) -> None:

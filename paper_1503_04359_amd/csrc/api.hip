@@ -58,6 +58,7 @@ struct Workspace {
   int32_t* done_host = nullptr;  /* pinned, 2 slots */
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t idle = nullptr;     /* recorded after the last kernel of a run */
+  std::vector<hipEvent_t> tev;   /* level-kernel timing events, 2 per launch */
   bool busy = false;
 
   void release() {
@@ -66,6 +67,7 @@ struct Workspace {
     if (done_host) (void)hipHostFree(done_host);
     for (auto& e : ev) if (e) (void)hipEventDestroy(e);
     if (idle) (void)hipEventDestroy(idle);
+    for (auto& e : tev) (void)hipEventDestroy(e);
     *this = Workspace();
   }
 };
@@ -82,6 +84,7 @@ struct dobfs_graph_s {
   int64_t words = 0, words_active = 0;
   int64_t n_nonisolated = 0, max_degree = 0, n_huge = 0;
   uint32_t flags = 0;
+  bool owns_csr = true;
   int64_t* off = nullptr;
   int32_t* idx = nullptr;
   uint64_t* iso = nullptr;
@@ -178,6 +181,7 @@ int check_params(const dobfs_params& p) {
   if (p.td_wave_cut < 0 || p.td_wave_cut > 4096 || p.td_huge_cut < 1 || p.bu_heavy_cut < 1)
     return fail(DOBFS_EINVAL, "degree cut-offs out of range");
   if (p.chunk_levels < 1 || p.chunk_levels > 1024) return fail(DOBFS_EINVAL, "chunk_levels out of range");
+  if (p.flags & ~DOBFS_RUN_TIME_KERNELS) return fail(DOBFS_EINVAL, "unknown run flag");
   return DOBFS_OK;
 }
 
@@ -210,6 +214,7 @@ void dobfs_default_params(dobfs_params* p) {
   p->td_huge_cut = 4096;
   p->bu_heavy_cut = 256;
   p->chunk_levels = 8;
+  p->flags = 0;
   p->seed = 0;
 }
 
@@ -235,8 +240,10 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
   *out = nullptr;
   if (!offsets || (!indices && m > 0)) return fail(DOBFS_EINVAL, "offsets/indices is NULL");
   if (n < 1 || n > 2147483647LL || m < 0) return fail(DOBFS_EINVAL, "n must be in [1, 2^31-1], m >= 0");
-  const uint32_t known = DOBFS_SRC_DEVICE | DOBFS_VALIDATE | DOBFS_VALIDATE_SYMMETRY | DOBFS_REINDEX_DEGREE;
+  const uint32_t known =
+      DOBFS_SRC_DEVICE | DOBFS_VALIDATE | DOBFS_VALIDATE_SYMMETRY | DOBFS_REINDEX_DEGREE | DOBFS_BORROW;
   if (flags & ~known) return fail(DOBFS_EINVAL, "unknown flag");
+  if ((flags & DOBFS_BORROW) && !(flags & DOBFS_SRC_DEVICE)) return fail(DOBFS_EINVAL, "DOBFS_BORROW needs DOBFS_SRC_DEVICE");
   if (flags & DOBFS_REINDEX_DEGREE) return fail(DOBFS_ENOTSUP, "degree relabelling is not built yet");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
@@ -254,21 +261,33 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
     dfree(counters);
     dfree(bad);
     if (status != DOBFS_OK) {
-      dfree(g->off); dfree(g->idx); dfree(g->iso);
+      if (g->owns_csr) {
+        dfree(g->off);
+        dfree(g->idx);
+      }
+      dfree(g->iso);
       delete g;
     }
     return status;
   };
   if ((e = hipGetDevice(&g->device)) != hipSuccess) return cleanup(fail(DOBFS_EDEVICE, "hipGetDevice", e));
   if ((e = level_grid(&g->grid)) != hipSuccess) return cleanup(fail(DOBFS_EDEVICE, "occupancy query", e));
-  if ((e = dalloc(&g->off, n + 1)) != hipSuccess || (e = dalloc(&g->idx, m)) != hipSuccess ||
-      (e = dalloc(&g->iso, g->words)) != hipSuccess || (e = dalloc(&counters, 4)) != hipSuccess ||
+  if (flags & DOBFS_BORROW) {
+    g->owns_csr = false;
+    g->off = const_cast<int64_t*>(offsets);
+    g->idx = const_cast<int32_t*>(indices);
+  } else if ((e = dalloc(&g->off, n + 1)) != hipSuccess || (e = dalloc(&g->idx, m)) != hipSuccess) {
+    return cleanup(fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "graph allocation", e));
+  }
+  if ((e = dalloc(&g->iso, g->words)) != hipSuccess || (e = dalloc(&counters, 4)) != hipSuccess ||
       (e = dalloc(&bad, 1)) != hipSuccess)
     return cleanup(fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "graph allocation", e));
-  const hipMemcpyKind kind = (flags & DOBFS_SRC_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  if ((e = hipMemcpyAsync(g->off, offsets, sizeof(int64_t) * (size_t)(n + 1), kind, s)) != hipSuccess ||
-      (m > 0 && (e = hipMemcpyAsync(g->idx, indices, sizeof(int32_t) * (size_t)m, kind, s)) != hipSuccess))
-    return cleanup(fail(DOBFS_EDEVICE, "graph copy", e));
+  if (g->owns_csr) {
+    const hipMemcpyKind kind = (flags & DOBFS_SRC_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if ((e = hipMemcpyAsync(g->off, offsets, sizeof(int64_t) * (size_t)(n + 1), kind, s)) != hipSuccess ||
+        (m > 0 && (e = hipMemcpyAsync(g->idx, indices, sizeof(int32_t) * (size_t)m, kind, s)) != hipSuccess))
+      return cleanup(fail(DOBFS_EDEVICE, "graph copy", e));
+  }
   /* Structure is always checked: a bad offset or index would make every
      later kernel read out of bounds. */
   if ((e = hipMemsetAsync(bad, 0, sizeof(int32_t), s)) != hipSuccess ||
@@ -308,8 +327,10 @@ int dobfs_graph_free(dobfs_graph_t g) {
     delete w;
   }
   g->pool.clear();
-  dfree(g->off);
-  dfree(g->idx);
+  if (g->owns_csr) {
+    dfree(g->off);
+    dfree(g->idx);
+  }
   dfree(g->iso);
   delete g;
   return DOBFS_OK;
@@ -322,7 +343,7 @@ int dobfs_graph_info(dobfs_graph_t g, dobfs_graph_info_t* info) {
   info->m = g->m;
   info->n_nonisolated = g->n_nonisolated;
   info->max_degree = g->max_degree;
-  info->device_bytes = (int64_t)sizeof(int64_t) * (g->n + 1) + (int64_t)sizeof(int32_t) * g->m +
+  info->device_bytes = (g->owns_csr ? (int64_t)sizeof(int64_t) * (g->n + 1) + (int64_t)sizeof(int32_t) * g->m : 0) +
                        (int64_t)sizeof(uint64_t) * g->words;
   info->flags = g->flags;
   return DOBFS_OK;
@@ -372,9 +393,21 @@ int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, co
 
   DOBFS_HIP(launch_init(gv, wv, root, first_direction(prm), g->grid, s), "init launch");
   const int K = prm.chunk_levels;
+  const bool timed = (prm.flags & DOBFS_RUN_TIME_KERNELS) != 0;
+  int64_t launches = 0;
   auto enqueue_chunk = [&](int slot) -> int {
     for (int i = 0; i < K; ++i) {
+      if (timed) {
+        while ((int64_t)w->tev.size() < 2 * (launches + 1)) {
+          hipEvent_t ev;
+          DOBFS_HIP(hipEventCreate(&ev), "timing event");
+          w->tev.push_back(ev);
+        }
+        DOBFS_HIP(hipEventRecord(w->tev[2 * launches], s), "timing event");
+      }
       DOBFS_HIP(launch_level(gv, wv, kp, g->grid, s), "level launch");
+      if (timed) DOBFS_HIP(hipEventRecord(w->tev[2 * launches + 1], s), "timing event");
+      ++launches;
       DOBFS_HIP(launch_aux(gv, wv, kp, g->grid, s), "aux launch");
     }
     DOBFS_HIP(hipMemcpyAsync(&w->done_host[slot], &w->ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, s),
@@ -393,10 +426,23 @@ int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, co
     if (w->done_host[c & 1]) break;
   }
   DOBFS_HIP(hipEventRecord(w->idle, s), "idle event");
-  if (stats) {
+  if (stats || timed) {
     Ctl ctl;
     DOBFS_HIP(hipMemcpyAsync(&ctl, w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "stats copy");
     DOBFS_HIP(hipStreamSynchronize(s), "stats sync");
+    if (!stats) return DOBFS_OK;
+    stats->level_launches = (int32_t)launches;
+    stats->level_kernel_ms = 0.0;
+    std::vector<float> kms;
+    if (timed) {
+      kms.resize((size_t)launches);
+      for (int64_t i = 0; i < launches; ++i) {
+        float ms = 0.f;
+        DOBFS_HIP(hipEventElapsedTime(&ms, w->tev[2 * i], w->tev[2 * i + 1]), "timing");
+        kms[(size_t)i] = ms;
+        stats->level_kernel_ms += ms;
+      }
+    }
     stats->levels = ctl.levels;
     stats->log_len = ctl.log_len < w->log_cap ? ctl.log_len : w->log_cap;
     stats->reached = ctl.reached;
@@ -408,6 +454,7 @@ int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, co
       if (k > 0)
         DOBFS_HIP(hipMemcpy(stats->log, w->log, sizeof(dobfs_level_rec) * (size_t)k, hipMemcpyDeviceToHost),
                   "log copy");
+      for (int32_t i = 0; i < k; ++i) stats->log[i].kernel_ms = i < (int32_t)kms.size() ? kms[(size_t)i] : 0.f;
     }
   }
   return DOBFS_OK;

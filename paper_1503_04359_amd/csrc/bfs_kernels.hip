@@ -147,6 +147,8 @@ __device__ void decide(const GView& g, const WView& w, const KParams& kp) {
     r.found = nfn;
     r.found_deg = mfn;
     r.t_end = wall_clock64();
+    r.kernel_ms = 0.f;
+    r.reserved = 0;
     w.log[c->log_len] = r;
     c->log_len = c->log_len + 1;
   }
