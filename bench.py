@@ -87,6 +87,8 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--roots", type=int, default=16)
     ap.add_argument("--policy", default="edge")
+    ap.add_argument("--reindex", choices=("on", "off"), default="on",
+                    help="degree relabelling inside the library (outputs stay in caller labels)")
     ap.add_argument("--cpu-scale", type=int, default=22)
     ap.add_argument("--cpu-roots", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -114,11 +116,20 @@ def main() -> int:
     log(f"[gpu] built kronecker scale {args.scale} on the device in {time.time() - t0:.1f}s "
         f"(n={g.n}, m={g.m})")
     roots = gg.sample_roots_device(g, args.roots, seed=args.seed + 1_000_000)
-    dg = dobfs.Graph.from_device_pointers(g.offsets_ptr, g.indices_ptr, g.n, g.m, borrow=True)
+    reindex = args.reindex == "on"
+    t0 = time.time()
+    dg = dobfs.Graph.from_device_pointers(g.offsets_ptr, g.indices_ptr, g.n, g.m, borrow=not reindex,
+                                          reindex=reindex)
+    torch.cuda.synchronize()
+    log(f"[gpu] graph resident ({'degree-relabelled copy' if reindex else 'borrowed in place'}) "
+        f"in {time.time() - t0:.1f}s")
+    n, m = g.n, g.m
+    if reindex:
+        g.free()  # the library keeps its own relabelled copy
     info = dg.info()
-    words_active = (info["n"] + 63) // 64
-    depth = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    words_active = ((info["n_nonisolated"] if reindex else info["n"]) + 63) // 64
+    depth = torch.empty(n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(n, dtype=torch.int32, device="cuda")
     params = dobfs.make_params(args.policy, flags=dobfs.RUN_TIME_KERNELS)
 
     def one_step(record):
@@ -186,9 +197,9 @@ def main() -> int:
            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
            "config": {"workload": f"kronecker scale {args.scale} edgefactor {args.edgefactor} "
                                   f"A/B/C 0.57/0.19/0.19 seed {args.seed}, {args.roots} roots, "
-                                  f"single-source DOBFS, policy {args.policy}",
-                      "scale": args.scale, "edgefactor": args.edgefactor, "n": g.n, "m": g.m,
-                      "roots": args.roots, "policy": args.policy, "reindex": False},
+                                  f"single-source DOBFS, policy {args.policy}, degree relabel {args.reindex}",
+                      "scale": args.scale, "edgefactor": args.edgefactor, "n": n, "m": m,
+                      "roots": args.roots, "policy": args.policy, "reindex": reindex},
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     dg.free()

@@ -92,7 +92,8 @@ typedef struct {
   int32_t td_wave_cut;     /* top-down: degree above which a whole wavefront
                               works on one vertex (default 16)              */
   int32_t td_huge_cut;     /* top-down: degree above which a vertex's edges
-                              are split over many wavefronts (default 4096) */
+                              are split over many wavefronts (default 256,
+                              at least 64)                                  */
   int32_t bu_heavy_cut;    /* bottom-up: degree above which a wavefront scans
                               one vertex cooperatively (default 256)        */
   int32_t chunk_levels;    /* levels enqueued per host check (default 8)    */

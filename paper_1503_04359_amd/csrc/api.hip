@@ -48,10 +48,10 @@ struct Workspace {
   uint64_t* fr0 = nullptr;
   uint64_t* fr1 = nullptr;
   int32_t* q0 = nullptr;
-  int32_t* q1 = nullptr;
   int32_t* huge_u = nullptr;
   uint32_t* huge_base = nullptr;
   int32_t* parent_scratch = nullptr;
+  int64_t* packed = nullptr;     /* relabelled graphs: internal (parent, depth) */
   Ctl* ctl = nullptr;
   dobfs_level_rec* log = nullptr;
   int32_t log_cap = 0;
@@ -62,8 +62,8 @@ struct Workspace {
   bool busy = false;
 
   void release() {
-    dfree(vis); dfree(fr0); dfree(fr1); dfree(q0); dfree(q1);
-    dfree(huge_u); dfree(huge_base); dfree(parent_scratch); dfree(ctl); dfree(log);
+    dfree(vis); dfree(fr0); dfree(fr1); dfree(q0);
+    dfree(huge_u); dfree(huge_base); dfree(parent_scratch); dfree(packed); dfree(ctl); dfree(log);
     if (done_host) (void)hipHostFree(done_host);
     for (auto& e : ev) if (e) (void)hipEventDestroy(e);
     if (idle) (void)hipEventDestroy(idle);
@@ -88,6 +88,8 @@ struct dobfs_graph_s {
   int64_t* off = nullptr;
   int32_t* idx = nullptr;
   uint64_t* iso = nullptr;
+  int32_t* new2old = nullptr;  /* relabelled graphs only */
+  int32_t* old2new = nullptr;
   int device = 0;
   int grid = 0;
   std::mutex mu;
@@ -98,8 +100,11 @@ struct dobfs_graph_s {
     g.off = off;
     g.idx = idx;
     g.iso = iso;
+    g.old2new = old2new;
+    g.new2old = new2old;
     g.n = n;
     g.m = m;
+    g.n_nonisolated = n_nonisolated;
     g.words = words;
     g.words_active = words_active;
     return g;
@@ -112,10 +117,10 @@ int alloc_workspace(dobfs_graph_s* g, Workspace* w) {
   const int64_t W = g->words;
   hipError_t e;
   if ((e = dalloc(&w->vis, W)) != hipSuccess || (e = dalloc(&w->fr0, W)) != hipSuccess ||
-      (e = dalloc(&w->fr1, W)) != hipSuccess || (e = dalloc(&w->q0, g->n)) != hipSuccess ||
-      (e = dalloc(&w->q1, g->n)) != hipSuccess || (e = dalloc(&w->huge_u, g->n_huge)) != hipSuccess ||
+      (e = dalloc(&w->fr1, W)) != hipSuccess || (e = dalloc(&w->q0, g->n)) != hipSuccess || (e = dalloc(&w->huge_u, g->n_huge)) != hipSuccess ||
       (e = dalloc(&w->huge_base, g->n_huge)) != hipSuccess || (e = dalloc(&w->ctl, 1)) != hipSuccess ||
-      (e = dalloc(&w->log, kLogCap)) != hipSuccess) {
+      (e = dalloc(&w->log, kLogCap)) != hipSuccess ||
+      (g->new2old && (e = dalloc(&w->packed, g->n)) != hipSuccess)) {
     w->release();
     return fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "workspace allocation", e);
   }
@@ -211,7 +216,7 @@ void dobfs_default_params(dobfs_params* p) {
   p->paper_div = 64;
   p->paper_bu_steps = 3;
   p->td_wave_cut = 16;
-  p->td_huge_cut = 4096;
+  p->td_huge_cut = 256;
   p->bu_heavy_cut = 256;
   p->chunk_levels = 8;
   p->flags = 0;
@@ -244,7 +249,6 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
       DOBFS_SRC_DEVICE | DOBFS_VALIDATE | DOBFS_VALIDATE_SYMMETRY | DOBFS_REINDEX_DEGREE | DOBFS_BORROW;
   if (flags & ~known) return fail(DOBFS_EINVAL, "unknown flag");
   if ((flags & DOBFS_BORROW) && !(flags & DOBFS_SRC_DEVICE)) return fail(DOBFS_EINVAL, "DOBFS_BORROW needs DOBFS_SRC_DEVICE");
-  if (flags & DOBFS_REINDEX_DEGREE) return fail(DOBFS_ENOTSUP, "degree relabelling is not built yet");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
   dobfs_graph_s* g = new (std::nothrow) dobfs_graph_s();
@@ -266,42 +270,79 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
         dfree(g->idx);
       }
       dfree(g->iso);
+      dfree(g->new2old);
+      dfree(g->old2new);
       delete g;
     }
     return status;
   };
   if ((e = hipGetDevice(&g->device)) != hipSuccess) return cleanup(fail(DOBFS_EDEVICE, "hipGetDevice", e));
   if ((e = level_grid(&g->grid)) != hipSuccess) return cleanup(fail(DOBFS_EDEVICE, "occupancy query", e));
-  if (flags & DOBFS_BORROW) {
+  const bool reindex = (flags & DOBFS_REINDEX_DEGREE) != 0;
+  /* src_off/src_idx: the CSR as given, on the device */
+  const int64_t* src_off = offsets;
+  const int32_t* src_idx = indices;
+  int64_t* tmp_off = nullptr;
+  int32_t* tmp_idx = nullptr;
+  auto drop_tmp = [&]() {
+    dfree(tmp_off);
+    dfree(tmp_idx);
+    tmp_off = nullptr;
+    tmp_idx = nullptr;
+  };
+  if ((flags & DOBFS_BORROW) && !reindex) {
     g->owns_csr = false;
     g->off = const_cast<int64_t*>(offsets);
     g->idx = const_cast<int32_t*>(indices);
-  } else if ((e = dalloc(&g->off, n + 1)) != hipSuccess || (e = dalloc(&g->idx, m)) != hipSuccess) {
-    return cleanup(fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "graph allocation", e));
+    src_off = g->off;
+    src_idx = g->idx;
+  } else if (!(flags & DOBFS_SRC_DEVICE) || !reindex) {
+    /* copy to the device: the graph itself, or the relabelling's source */
+    int64_t** po = reindex ? &tmp_off : &g->off;
+    int32_t** pi = reindex ? &tmp_idx : &g->idx;
+    if ((e = dalloc(po, n + 1)) != hipSuccess || (e = dalloc(pi, m)) != hipSuccess) {
+      drop_tmp();
+      return cleanup(fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "graph allocation", e));
+    }
+    const hipMemcpyKind kind = (flags & DOBFS_SRC_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if ((e = hipMemcpyAsync(*po, offsets, sizeof(int64_t) * (size_t)(n + 1), kind, s)) != hipSuccess ||
+        (m > 0 && (e = hipMemcpyAsync(*pi, indices, sizeof(int32_t) * (size_t)m, kind, s)) != hipSuccess)) {
+      drop_tmp();
+      return cleanup(fail(DOBFS_EDEVICE, "graph copy", e));
+    }
+    src_off = *po;
+    src_idx = *pi;
   }
   if ((e = dalloc(&g->iso, g->words)) != hipSuccess || (e = dalloc(&counters, 4)) != hipSuccess ||
-      (e = dalloc(&bad, 1)) != hipSuccess)
+      (e = dalloc(&bad, 1)) != hipSuccess) {
+    drop_tmp();
     return cleanup(fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "graph allocation", e));
-  if (g->owns_csr) {
-    const hipMemcpyKind kind = (flags & DOBFS_SRC_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    if ((e = hipMemcpyAsync(g->off, offsets, sizeof(int64_t) * (size_t)(n + 1), kind, s)) != hipSuccess ||
-        (m > 0 && (e = hipMemcpyAsync(g->idx, indices, sizeof(int32_t) * (size_t)m, kind, s)) != hipSuccess))
-      return cleanup(fail(DOBFS_EDEVICE, "graph copy", e));
   }
   /* Structure is always checked: a bad offset or index would make every
      later kernel read out of bounds. */
   if ((e = hipMemsetAsync(bad, 0, sizeof(int32_t), s)) != hipSuccess ||
-      (e = launch_validate(g->off, g->idx, n, m, (flags & DOBFS_VALIDATE_SYMMETRY) ? 1 : 0, bad, g->grid, s)) !=
-          hipSuccess)
+      (e = launch_validate(src_off, src_idx, n, m, (flags & DOBFS_VALIDATE_SYMMETRY) ? 1 : 0, bad, g->grid, s)) !=
+          hipSuccess) {
+    drop_tmp();
     return cleanup(fail(DOBFS_EDEVICE, "validation launch", e));
+  }
   int32_t bad_h = 0;
   if ((e = hipMemcpyAsync(&bad_h, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-      (e = hipStreamSynchronize(s)) != hipSuccess)
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
+    drop_tmp();
     return cleanup(fail(DOBFS_EDEVICE, "validation", e));
+  }
   if (bad_h) {
     static const char* what[] = {"", "offsets not monotone or not ending at m", "neighbour ID out of range",
                                  "self-loop", "missing reverse edge (CSR not symmetric or rows unsorted)"};
+    drop_tmp();
     return cleanup(fail(DOBFS_EINVAL, what[bad_h < 5 ? bad_h : 0]));
+  }
+  if (reindex) {
+    std::string err;
+    st = build_reindexed(src_off, src_idx, n, m, g->grid, s, &g->off, &g->idx, &g->new2old, &g->old2new, &err);
+    drop_tmp();
+    if (st != DOBFS_OK) return cleanup(fail(st, err.c_str()));
   }
   if ((e = hipMemsetAsync(counters, 0, 4 * sizeof(int64_t), s)) != hipSuccess ||
       (e = launch_graph_scan(g->off, n, g->iso, counters, g->grid, s)) != hipSuccess)
@@ -313,7 +354,8 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
   g->n_nonisolated = ch[0];
   g->max_degree = ch[1];
   g->n_huge = ch[2];
-  g->words_active = g->words;
+  /* relabelled graphs keep every degree-0 vertex in a suffix */
+  g->words_active = reindex ? (g->n_nonisolated + 63) / 64 : g->words;
   (void)st;
   *out = g;
   return cleanup(DOBFS_OK);
@@ -332,6 +374,8 @@ int dobfs_graph_free(dobfs_graph_t g) {
     dfree(g->idx);
   }
   dfree(g->iso);
+  dfree(g->new2old);
+  dfree(g->old2new);
   delete g;
   return DOBFS_OK;
 }
@@ -344,7 +388,7 @@ int dobfs_graph_info(dobfs_graph_t g, dobfs_graph_info_t* info) {
   info->n_nonisolated = g->n_nonisolated;
   info->max_degree = g->max_degree;
   info->device_bytes = (g->owns_csr ? (int64_t)sizeof(int64_t) * (g->n + 1) + (int64_t)sizeof(int32_t) * g->m : 0) +
-                       (int64_t)sizeof(uint64_t) * g->words;
+                       (int64_t)sizeof(uint64_t) * g->words + (g->new2old ? 8 * g->n : 0);
   info->flags = g->flags;
   return DOBFS_OK;
 }
@@ -367,7 +411,7 @@ int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, co
     ~Guard() { release_workspace(g, w); }
   } guard{g, w};
 
-  if (!parent) {
+  if (!parent && !g->new2old) {
     if (!w->parent_scratch) {
       hipError_t e = dalloc(&w->parent_scratch, g->n);
       if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "parent scratch", e);
@@ -380,11 +424,11 @@ int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, co
   wv.fr0 = w->fr0;
   wv.fr1 = w->fr1;
   wv.q0 = w->q0;
-  wv.q1 = w->q1;
   wv.huge_u = w->huge_u;
   wv.huge_base = w->huge_base;
   wv.depth = depth;
   wv.parent = parent;
+  wv.packed = g->new2old ? w->packed : nullptr;
   wv.ctl = w->ctl;
   wv.log = w->log;
   wv.log_cap = w->log_cap;
@@ -425,6 +469,7 @@ int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, co
     DOBFS_HIP(hipEventSynchronize(w->ev[c & 1]), "level chunk");
     if (w->done_host[c & 1]) break;
   }
+  if (g->new2old) DOBFS_HIP(launch_finalize(gv, wv, root, g->grid, s), "finalize launch");
   DOBFS_HIP(hipEventRecord(w->idle, s), "idle event");
   if (stats || timed) {
     Ctl ctl;

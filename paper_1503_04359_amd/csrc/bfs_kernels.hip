@@ -20,18 +20,20 @@
  *     store: bottom-up needs no atomics.  Vertices above bu_heavy_cut are
  *     scanned 64 neighbours at a time by the whole wave, stopping at the
  *     first hit.
+ *   - bottom-up work inside a word is balanced across lanes: adjacency
+ *     lists are consumed in rounds of growing per-vertex quotas laid end to
+ *     end over the 64 lanes (see bottom_up).
  *   - top-down: degree-binned (the virtual-warp idea of Section 2.1 on
  *     64-wide wavefronts): a lane per vertex up to td_wave_cut, a wavefront
  *     per vertex up to td_huge_cut, and above that the vertex's edges are
  *     cut into kHugeChunk-edge tasks spread over all wavefronts by the aux
- *     kernel.  Queue appends are aggregated per wavefront (one atomic per
- *     ballot).
- *   - frontier representations: top-down levels read a queue and also set
- *     the next frontier's bitmap bits (so a following bottom-up level can
- *     probe it); a bottom-up level followed by top-down converts its bitmap
- *     into a queue in the aux kernel.  Bitmap buffer F[L%2] holds F_L; a
- *     top-down level clears the words of F_L it reads so F[L%2] is zero when
- *     level L+1 starts writing F_{L+2} into it.
+ *     kernel.
+ *   - frontier representations: every level produces the next frontier as
+ *     a bitmap only (top-down sets bits with atomic OR, bottom-up writes
+ *     whole words).  Before a top-down level the aux kernel turns that
+ *     bitmap into a queue with one atomic per workgroup, and clears the
+ *     other bitmap buffer, which the top-down level then fills.  Bitmap
+ *     buffer F[L%2] holds F_L.
  */
 #include <hip/hip_runtime.h>
 
@@ -42,11 +44,6 @@ namespace {
 
 __device__ __forceinline__ int lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
-}
-
-/* Number of set bits of `m` below the calling lane. */
-__device__ __forceinline__ int mask_rank(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
 
 __device__ __forceinline__ bool test_bit(const uint64_t* bm, int32_t v) {
@@ -71,7 +68,7 @@ __device__ __forceinline__ int64_t wave_sum(int64_t x) {
 }
 
 /* Per-workgroup reduction of the accumulators, one atomic per counter. */
-__device__ void flush_acc(Ctl* ctl, Acc a, bool add_found) {
+__device__ void flush_acc(Ctl* ctl, Acc a) {
   __shared__ int64_t part[4][kBlock / kWave];
   const int lane = lane_id(), wv = threadIdx.x / kWave;
   a.found = wave_sum(a.found);
@@ -89,7 +86,7 @@ __device__ void flush_acc(Ctl* ctl, Acc a, bool add_found) {
     int64_t s[4] = {0, 0, 0, 0};
     for (int k = 0; k < 4; ++k)
       for (int j = 0; j < kBlock / kWave; ++j) s[k] += part[k][j];
-    if (add_found && s[0]) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->nf_next), (unsigned long long)s[0]);
+    if (s[0]) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->nf_next), (unsigned long long)s[0]);
     if (s[1]) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->mf_next), (unsigned long long)s[1]);
     if (s[2]) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->checked), (unsigned long long)s[2]);
     if (s[3]) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->scanned), (unsigned long long)s[3]);
@@ -179,8 +176,7 @@ __device__ void decide(const GView& g, const WView& w, const KParams& kp) {
     }
   }
   if (dir == kDirTD && next == kDirBU) c->bu_phases = c->bu_phases + 1;
-  c->aux = (!c->done && dir == kDirBU && next == kDirTD) ? kAuxToQueue : kAuxNone;
-  if (dir == kDirTD) c->qsel = c->qsel ^ 1;
+  c->aux = (!c->done && next == kDirTD) ? kAuxToQueue : kAuxNone;
   c->bu_run = bu_run;
   c->n_f = nfn;
   c->m_f = mfn;
@@ -195,32 +191,41 @@ __device__ void decide(const GView& g, const WView& w, const KParams& kp) {
   c->q_fill = 0;
 }
 
-/* Wave-aggregated append of the claimed vertices; writes their labels and
-   next-frontier bits and accumulates their degrees. */
-__device__ __forceinline__ void emit(const GView& g, const WView& w, int32_t* q_nxt, uint64_t* f_nxt,
-                                     bool won, int32_t v, int32_t u, int32_t L, int lane, Acc& a) {
-  const uint64_t m = __ballot(won);
-  if (m == 0ull) return;
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  unsigned long long base = 0;
-  if (lane == leader)
-    base = atomicAdd(reinterpret_cast<unsigned long long*>(&w.ctl->nf_next), (unsigned long long)__popcll(m));
-  base = __shfl(base, leader);
-  if (won) {
-    q_nxt[base + mask_rank(m)] = v;
-    w.depth[v] = L + 1;
-    w.parent[v] = u;
-    atomicOr(reinterpret_cast<unsigned long long*>(f_nxt + (v >> 6)), 1ull << (v & 63));
-    a.found_deg += g.off[v + 1] - g.off[v];
+/* Inclusive prefix sum over the wavefront. */
+__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
   }
+  return x;
+}
+
+/* Writes the labels of a newly reached vertex: the caller's depth/parent
+   arrays, or (relabelled graphs) one packed (parent << 32 | depth) word in
+   internal labels that the finalize kernel maps back. */
+__device__ __forceinline__ void store_labels(const WView& w, int32_t v, int32_t d, int32_t p) {
+  if (w.packed) {
+    w.packed[v] = (int64_t)(((uint64_t)(uint32_t)p << 32) | (uint64_t)(uint32_t)d);
+  } else {
+    w.depth[v] = d;
+    w.parent[v] = p;
+  }
+}
+
+/* Bookkeeping of a vertex v claimed from u at level L: labels, next-frontier
+   bit and the degree sum that feeds the switching rule. */
+__device__ __forceinline__ void claimed(const GView& g, const WView& w, uint64_t* f_nxt, int32_t v, int32_t u,
+                                        int32_t L, Acc& a) {
+  store_labels(w, v, L + 1, u);
+  atomicOr(reinterpret_cast<unsigned long long*>(f_nxt + (v >> 6)), 1ull << (v & 63));
+  a.found += 1;
+  a.found_deg += g.off[v + 1] - g.off[v];
 }
 
 __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int32_t L, Acc& a) {
   Ctl* c = w.ctl;
   const int64_t nf = c->n_f;
-  const int32_t* q_cur = c->qsel ? w.q1 : w.q0;
-  int32_t* q_nxt = c->qsel ? w.q0 : w.q1;
-  uint64_t* f_cur = (L & 1) ? w.fr1 : w.fr0;
+  const int32_t* q_cur = w.q0;
   uint64_t* f_nxt = (L & 1) ? w.fr0 : w.fr1;
   const int lane = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -234,26 +239,18 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
     int64_t beg = 0, deg = 0;
     if (valid) {
       u = q_cur[i];
-      f_cur[u >> 6] = 0ull;  /* F_L is consumed by this level */
       beg = g.off[u];
       deg = g.off[u + 1] - beg;
     }
     a.checked += deg;
-    const bool huge = deg > huge_cut;
+    const bool huge = valid && deg > huge_cut;
     const bool med = !huge && deg > wave_cut;
 
     /* lane per vertex */
     const int64_t sdeg = (valid && !huge && !med) ? deg : 0;
-    for (int64_t j = 0;; ++j) {
-      const bool act = j < sdeg;
-      if (__ballot(act) == 0ull) break;
-      int32_t v = 0;
-      bool won = false;
-      if (act) {
-        v = g.idx[beg + j];
-        won = try_claim(w.vis, v);
-      }
-      emit(g, w, q_nxt, f_nxt, won, v, u, L, lane, a);
+    for (int64_t j = 0; j < sdeg; ++j) {
+      const int32_t v = g.idx[beg + j];
+      if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, u, L, a);
     }
 
     /* wavefront per vertex */
@@ -264,38 +261,50 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
       const int32_t uu = __shfl(u, src);
       const int64_t bb = __shfl(beg, src);
       const int64_t dd = __shfl(deg, src);
-      for (int64_t k0 = 0; k0 < dd; k0 += kWave) {
-        const int64_t k = k0 + lane;
-        const bool act = k < dd;
-        int32_t v = 0;
-        bool won = false;
-        if (act) {
-          v = g.idx[bb + k];
-          won = try_claim(w.vis, v);
-        }
-        emit(g, w, q_nxt, f_nxt, won, v, uu, L, lane, a);
+      for (int64_t k = lane; k < dd; k += kWave) {
+        const int32_t v = g.idx[bb + k];
+        if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, uu, L, a);
       }
     }
 
-    /* split vertices: defer to the aux kernel */
-    if (huge) {
-      const unsigned long long nch = (unsigned long long)((deg + kHugeChunk - 1) / kHugeChunk);
-      const unsigned long long old =
-          atomicAdd(reinterpret_cast<unsigned long long*>(&c->huge_pack), (1ull << 32) | nch);
-      const uint32_t slot = (uint32_t)(old >> 32);
-      w.huge_u[slot] = u;
-      w.huge_base[slot] = (uint32_t)(old & 0xFFFFFFFFull);
+    /* split vertices: defer to the aux kernel.  One atomic per wavefront
+       reserves consecutive list entries and consecutive chunk numbers, so
+       chunk bases increase with the entry index. */
+    const uint64_t hm = __ballot(huge);
+    if (hm) {
+      const int nch = huge ? (int)((deg + kHugeChunk - 1) / kHugeChunk) : 0;
+      const int incl = wave_incl_scan(nch, lane);
+      const int tot = __shfl(incl, kWave - 1);
+      unsigned long long old = 0;
+      if (lane == 0)
+        old = atomicAdd(reinterpret_cast<unsigned long long*>(&c->huge_pack),
+                        ((unsigned long long)__popcll(hm) << 32) | (unsigned long long)tot);
+      old = __shfl(old, 0);
+      if (huge) {
+        const uint32_t slot = (uint32_t)(old >> 32) + (uint32_t)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(hm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hm, 0));
+        w.huge_u[slot] = u;
+        w.huge_base[slot] = (uint32_t)(old & 0xFFFFFFFFull) + (uint32_t)(incl - nch);
+      }
     }
   }
 }
 
+/* Bottom-up level.  One wavefront per 64-vertex word.  The unvisited
+   vertices' adjacency lists are scanned in rounds: in round r each vertex
+   still searching contributes its next min(2^r, remaining) neighbours, the
+   contributions are laid end to end and cut into 64-entry chunks, and each
+   lane tests one neighbour of one chunk.  Every lane does useful work even
+   when degrees differ inside the word, neighbour IDs of one vertex are read
+   contiguously, and a vertex stops at the round in which it finds its first
+   frontier neighbour (its parent: the first hit in adjacency order). */
 __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int32_t L, Acc& a) {
   const uint64_t* f_cur = (L & 1) ? w.fr1 : w.fr0;
   uint64_t* f_nxt = (L & 1) ? w.fr0 : w.fr1;
   const int lane = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  const int64_t heavy_cut = kp.bu_heavy_cut;
+  const int max_quota = kp.bu_heavy_cut < kWave ? kWave : kp.bu_heavy_cut;
 
   for (int64_t wd = wave; wd < g.words_active; wd += nwaves) {
     const uint64_t vis = w.vis[wd];
@@ -305,61 +314,64 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
     }
     const int32_t v = (int32_t)(wd * kWave + lane);
     const bool unv = ((vis >> lane) & 1ull) == 0ull;  /* bits >= n are set */
-    int64_t beg = 0, end = 0;
+    int64_t pos = 0, end = 0;
     if (unv) {
-      beg = g.off[v];
+      pos = g.off[v];
       end = g.off[v + 1];
     }
-    const int64_t deg = end - beg;
-    const bool heavy = unv && deg > heavy_cut;
+    const int64_t deg = end - pos;
     a.scanned += unv ? 1 : 0;
     bool found = false;
     int32_t par = -1;
-    if (unv && !heavy) {
-      int64_t e = beg;
-      for (; e < end; ++e) {
-        const int32_t u = g.idx[e];
-        if (test_bit(f_cur, u)) {
-          found = true;
-          par = u;
-          break;
-        }
-      }
-      a.checked += found ? (e - beg + 1) : deg;
-    }
-    uint64_t hm = __ballot(heavy);
-    while (hm) {
-      const int src = __ffsll((unsigned long long)hm) - 1;
-      hm &= hm - 1;
-      const int64_t bb = __shfl(beg, src), ee = __shfl(end, src);
-      int32_t hp = -1;
-      int64_t pos = ee - bb;
-      for (int64_t k0 = bb; k0 < ee; k0 += kWave) {
-        const int64_t e = k0 + lane;
+    int quota = 1;
+    while (__ballot(!found && pos < end)) {
+      const int take = (!found && pos < end) ? (int)min(end - pos, (int64_t)quota) : 0;
+      const int incl = wave_incl_scan(take, lane);
+      const int excl = incl - take;
+      const int total = __shfl(incl, kWave - 1);
+      for (int c0 = 0; c0 < total; c0 += kWave) {
+        /* owner of concatenated position p: first lane whose incl > p */
+        const int p = c0 + lane;
+        int lo = 0;  /* lanes with incl <= p (incl is non-decreasing) */
+        for (int step = kWave / 2; step > 0; step >>= 1)
+          if (__shfl(incl, lo + step - 1) <= p) lo += step;
+        const int o = lo < kWave ? lo : kWave - 1;
+        const int64_t opos = __shfl(pos, o);
+        const int oexcl = __shfl(excl, o);
         int32_t u = 0;
         bool hit = false;
-        if (e < ee) {
-          u = g.idx[e];
+        if (p < total) {
+          u = g.idx[opos + (p - oexcl)];
           hit = test_bit(f_cur, u);
         }
-        const uint64_t hmask = __ballot(hit);
-        if (hmask) {
-          const int first = __ffsll((unsigned long long)hmask) - 1;
-          hp = __shfl(u, first);
-          pos = k0 - bb + first + 1;
-          break;
+        const uint64_t H = __ballot(hit);
+        /* this lane's slice of the chunk: [sa, sb) */
+        const int sa = max(excl, c0) - c0, sb = min(incl, c0 + kWave) - c0;
+        int src = lane;
+        bool got = false;
+        if (take > 0 && sa < sb && !found) {
+          const uint64_t span = (sb - sa >= 64) ? ~0ull : (((1ull << (sb - sa)) - 1ull) << sa);
+          const uint64_t h = H & span;
+          if (h) {
+            src = __ffsll((unsigned long long)h) - 1;
+            got = true;
+            a.checked += src - sa + 1;
+          } else {
+            a.checked += sb - sa;
+          }
+        }
+        const int32_t pu = __shfl(u, src);
+        if (got) {
+          found = true;
+          par = pu;
         }
       }
-      if (lane == src) {
-        found = hp >= 0;
-        par = hp;
-        a.checked += pos;
-      }
+      pos += take;
+      if (quota < max_quota) quota <<= 1;
     }
     const uint64_t fm = __ballot(found);
     if (found) {
-      w.depth[v] = L + 1;
-      w.parent[v] = par;
+      store_labels(w, v, L + 1, par);
       a.found_deg += deg;
       a.found += 1;
     }
@@ -378,7 +390,7 @@ __global__ void __launch_bounds__(kBlock) k_level(GView g, WView w, KParams kp) 
   Acc a = {0, 0, 0, 0};
   if (dir == kDirTD) top_down(g, w, kp, L, a);
   else bottom_up(g, w, kp, L, a);
-  flush_acc(c, a, dir == kDirBU);
+  flush_acc(c, a);
   if (last_block(c)) {
     if (dir == kDirTD && ld_agent(&c->huge_pack) != 0ull) {
       c->ticket = 0;
@@ -389,8 +401,29 @@ __global__ void __launch_bounds__(kBlock) k_level(GView g, WView w, KParams kp) 
   }
 }
 
-/* Expands the split top-down vertices (kAuxHuge) or turns the bottom-up
-   frontier bitmap into a queue (kAuxToQueue). */
+/* Exclusive prefix sum over the workgroup; *total gets the sum. */
+__device__ int64_t block_excl_scan(int64_t x, int64_t* total) {
+  __shared__ int64_t wsum[kBlock / kWave];
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  int64_t incl = x;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) wsum[wv] = incl;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+  for (int j = 0; j < kBlock / kWave; ++j) {
+    if (j < wv) before += wsum[j];
+    all += wsum[j];
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - x;
+}
+
+/* Expands the split top-down vertices (kAuxHuge) or turns the frontier
+   bitmap of a level about to run top-down into its queue (kAuxToQueue). */
 __global__ void __launch_bounds__(kBlock) k_aux(GView g, WView w, KParams kp) {
   Ctl* c = w.ctl;
   if (c->done) return;
@@ -406,31 +439,31 @@ __global__ void __launch_bounds__(kBlock) k_aux(GView g, WView w, KParams kp) {
     const unsigned long long pack = c->huge_pack;
     const int64_t nent = (int64_t)(pack >> 32);
     const int64_t nchunks = (int64_t)(pack & 0xFFFFFFFFull);
-    int32_t* q_nxt = c->qsel ? w.q0 : w.q1;
     uint64_t* f_nxt = (L & 1) ? w.fr0 : w.fr1;
-    for (int64_t ch = wave; ch < nchunks; ch += nwaves) {
-      int64_t lo = 0, hi = nent - 1;  /* last entry with base <= ch */
+    /* each wavefront takes a contiguous range of chunks: one search for
+       the first chunk's entry, then a forward walk */
+    const int64_t per = (nchunks + nwaves - 1) / nwaves;
+    const int64_t c0 = min(nchunks, wave * per), c1 = min(nchunks, c0 + per);
+    int64_t lo = 0;
+    if (c0 < c1) {
+      int64_t hi = nent - 1;  /* last entry with base <= c0 */
       while (lo < hi) {
         const int64_t mid = (lo + hi + 1) >> 1;
-        if ((int64_t)w.huge_base[mid] <= ch) lo = mid; else hi = mid - 1;
+        if ((int64_t)w.huge_base[mid] <= c0) lo = mid; else hi = mid - 1;
       }
+    }
+    for (int64_t ch = c0; ch < c1; ++ch) {
+      while (lo + 1 < nent && (int64_t)w.huge_base[lo + 1] <= ch) ++lo;
       const int32_t u = w.huge_u[lo];
       const int64_t rb = g.off[u], re = g.off[u + 1];
       const int64_t beg = rb + (ch - (int64_t)w.huge_base[lo]) * kHugeChunk;
       const int64_t end = min(re, beg + (int64_t)kHugeChunk);
-      for (int64_t k0 = beg; k0 < end; k0 += kWave) {
-        const int64_t k = k0 + lane;
-        const bool act = k < end;
-        int32_t v = 0;
-        bool won = false;
-        if (act) {
-          v = g.idx[k];
-          won = try_claim(w.vis, v);
-        }
-        emit(g, w, q_nxt, f_nxt, won, v, u, L, lane, a);
+      for (int64_t k = beg + lane; k < end; k += kWave) {
+        const int32_t v = g.idx[k];
+        if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, u, L, a);
       }
     }
-    flush_acc(c, a, false);
+    flush_acc(c, a);
     if (last_block(c)) {
       c->aux = kAuxNone;
       decide(g, w, kp);
@@ -438,34 +471,42 @@ __global__ void __launch_bounds__(kBlock) k_aux(GView g, WView w, KParams kp) {
     return;
   }
 
-  /* kAuxToQueue: level L is top-down after a bottom-up level. */
+  /* kAuxToQueue: level L runs top-down.  Each workgroup owns a contiguous
+     range of frontier words: it counts their bits, reserves its queue slice
+     with one atomic, then writes the vertices; the other bitmap buffer
+     (read by level L-1 or already clear) is zeroed for level L to fill. */
   const uint64_t* f_cur = (L & 1) ? w.fr1 : w.fr0;
   uint64_t* f_old = (L & 1) ? w.fr0 : w.fr1;
-  int32_t* q = c->qsel ? w.q1 : w.q0;
-  for (int64_t b = wave * kWave; b < g.words_active; b += nwaves * kWave) {
-    const int64_t wd = b + lane;
-    uint64_t word = 0ull;
-    if (wd < g.words_active) {
-      word = f_cur[wd];
-      f_old[wd] = 0ull;
-    }
-    int64_t cnt = __popcll(word);
-    /* inclusive wave prefix sum of counts */
-    int64_t incl = cnt;
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int64_t y = __shfl_up(incl, o);
-      if (lane >= o) incl += y;
-    }
-    const int64_t total = __shfl(incl, kWave - 1);
-    if (total == 0) continue;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(&c->q_fill), (unsigned long long)total);
-    base = __shfl(base, 0);
-    int64_t pos = (int64_t)base + incl - cnt;
-    while (word) {
-      const int bit = __ffsll((unsigned long long)word) - 1;
-      word &= word - 1;
-      q[pos++] = (int32_t)(wd * kWave + bit);
+  int32_t* q = w.q0;
+  const int64_t W = g.words_active;
+  const int64_t per = (W + gridDim.x - 1) / gridDim.x;
+  const int64_t w0 = min(W, (int64_t)blockIdx.x * per), w1 = min(W, w0 + per);
+  int64_t cnt = 0;
+  for (int64_t wd = w0 + threadIdx.x; wd < w1; wd += blockDim.x) {
+    cnt += __popcll(f_cur[wd]);
+    f_old[wd] = 0ull;
+  }
+  int64_t blk_total = 0;
+  (void)block_excl_scan(cnt, &blk_total);
+  __shared__ int64_t s_base;
+  if (threadIdx.x == 0)
+    s_base = blk_total ? (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&c->q_fill),
+                                            (unsigned long long)blk_total)
+                       : 0;
+  __syncthreads();
+  int64_t run = s_base;
+  if (blk_total) {
+    for (int64_t b = w0; b < w1; b += blockDim.x) {
+      const int64_t wd = b + threadIdx.x;
+      uint64_t word = wd < w1 ? f_cur[wd] : 0ull;
+      int64_t chunk_total = 0;
+      int64_t pos = run + block_excl_scan(__popcll(word), &chunk_total);
+      while (word) {
+        const int bit = __ffsll((unsigned long long)word) - 1;
+        word &= word - 1;
+        q[pos++] = (int32_t)(wd * kWave + bit);
+      }
+      run += chunk_total;
     }
   }
   if (last_block(c)) {
@@ -477,9 +518,14 @@ __global__ void __launch_bounds__(kBlock) k_aux(GView g, WView w, KParams kp) {
 __global__ void __launch_bounds__(kBlock) k_init_fill(GView g, WView w) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = tid; i < g.n; i += nth) {
-    w.depth[i] = -1;
-    w.parent[i] = -1;
+  if (w.packed) {
+    /* internal labels: only non-isolated vertices can be reached */
+    for (int64_t i = tid; i < g.n_nonisolated; i += nth) w.packed[i] = -1;
+  } else {
+    for (int64_t i = tid; i < g.n; i += nth) {
+      w.depth[i] = -1;
+      w.parent[i] = -1;
+    }
   }
   for (int64_t i = tid; i < g.words; i += nth) {
     w.vis[i] = g.iso[i];
@@ -488,20 +534,19 @@ __global__ void __launch_bounds__(kBlock) k_init_fill(GView g, WView w) {
   }
 }
 
-__global__ void k_init_root(GView g, WView w, int32_t root, int32_t first_dir) {
+__global__ void k_init_root(GView g, WView w, int32_t root_caller, int32_t first_dir) {
   if (threadIdx.x != 0) return;
+  const int32_t root = g.old2new ? g.old2new[root_caller] : root_caller;
   const uint64_t bit = 1ull << (root & 63);
   w.vis[root >> 6] |= bit;
   w.fr0[root >> 6] |= bit;
-  w.depth[root] = 0;
-  w.parent[root] = root;
+  store_labels(w, root, 0, root);
   w.q0[0] = root;
   const int64_t dr = g.off[root + 1] - g.off[root];
   Ctl* c = w.ctl;
   c->level = 0;
   c->dir = first_dir;
   c->done = 0;
-  c->qsel = 0;
   c->aux = kAuxNone;
   c->bu_run = 0;
   c->bu_phases = first_dir == kDirBU ? 1 : 0;
@@ -521,6 +566,27 @@ __global__ void k_init_root(GView g, WView w, int32_t root, int32_t first_dir) {
   c->reached_deg = dr;
   c->checked_total = 0;
   c->t_begin = wall_clock64();
+}
+
+/* Relabelled graphs: caller-label outputs from the packed internal words.
+   Caller vertex x has internal label old2new[x]; internal labels at or
+   beyond n_nonisolated have degree 0 and are unreached unless x is the
+   root. */
+__global__ void __launch_bounds__(kBlock) k_finalize(GView g, WView w, int32_t root_caller) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = tid; x < g.n; x += nth) {
+    const int32_t v = g.old2new[x];
+    int32_t d = -1, p = -1;
+    if ((int64_t)v < g.n_nonisolated || x == root_caller) {
+      const uint64_t rec = (uint64_t)w.packed[v];
+      d = (int32_t)(uint32_t)(rec & 0xFFFFFFFFull);
+      const int32_t pn = (int32_t)(uint32_t)(rec >> 32);
+      p = pn >= 0 ? g.new2old[pn] : -1;
+    }
+    w.depth[x] = d;
+    if (w.parent) w.parent[x] = p;
+  }
 }
 
 }  // namespace
@@ -547,6 +613,11 @@ hipError_t launch_init(const GView& g, const WView& w, int64_t root, int32_t fir
 
 hipError_t launch_level(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_level, dim3(grid), dim3(kBlock), 0, s, g, w, kp);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const GView& g, const WView& w, int64_t root, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kBlock), 0, s, g, w, (int32_t)root);
   return hipGetLastError();
 }
 

@@ -15,7 +15,8 @@
  * Workspace of one traversal (reused by later traversals of the graph):
  *   vis      uint64[W]    visited set (bit per vertex)
  *   fr[2]    uint64[W]    frontier bitmaps of levels L (even/odd)
- *   q[2]     int32[n]     frontier queues for top-down levels
+ *   q        int32[n]     frontier queue of a top-down level (rebuilt from
+ *                         the frontier bitmap before each such level)
  *   huge_u / huge_base    top-down vertices whose edges are split across
  *                         wavefronts, with the first chunk index of each
  *   ctl                   level state and counters (below)
@@ -27,26 +28,28 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "dobfs.h"
 
 namespace dobfs {
 
 constexpr int kBlock = 256;          /* threads per workgroup (4 wavefronts) */
 constexpr int kWave = 64;
-constexpr int kHugeChunk = 2048;     /* edges per wavefront task for split vertices */
-constexpr int kMinHugeCut = 256;     /* lower bound of td_huge_cut */
+constexpr int kHugeChunk = 512;      /* edges per wavefront task for split vertices */
+constexpr int kMinHugeCut = 64;      /* lower bound of td_huge_cut */
 constexpr int kDirTD = 0;
 constexpr int kDirBU = 1;
 constexpr int kAuxNone = 0;
 constexpr int kAuxHuge = 1;          /* split top-down vertices still to expand */
-constexpr int kAuxToQueue = 2;       /* bottom-up -> top-down: bitmap to queue */
+constexpr int kAuxToQueue = 2;       /* next level top-down: bitmap to queue */
 
 /* Level state, advanced on the device by the last workgroup of each level. */
 struct Ctl {
   int32_t level;        /* L: frontier = vertices of depth L              */
   int32_t dir;          /* direction of level L                           */
   int32_t done;         /* set when a level finds no new vertex           */
-  int32_t qsel;         /* q[qsel] holds the level-L queue (top-down)     */
+  int32_t pad2;
   int32_t aux;          /* kAux*: work for the aux kernel of this level   */
   int32_t bu_run;       /* consecutive bottom-up levels just completed    */
   int32_t bu_phases;    /* bottom-up phases started so far                */
@@ -55,7 +58,7 @@ struct Ctl {
   int32_t pad0;
   int64_t n_f, m_f, m_u;
   /* accumulators of the level in progress */
-  int64_t nf_next;      /* also the top-down queue append cursor          */
+  int64_t nf_next;
   int64_t mf_next;
   int64_t checked;
   int64_t scanned;
@@ -79,7 +82,10 @@ struct GView {
   const int64_t* off;
   const int32_t* idx;
   const uint64_t* iso;
+  const int32_t* old2new;  /* relabelled graphs: caller ID -> internal ID  */
+  const int32_t* new2old;  /* relabelled graphs: internal ID -> caller ID  */
   int64_t n, m;
+  int64_t n_nonisolated;
   int64_t words;         /* ceil(n/64)                                     */
   int64_t words_active;  /* words that may hold an unvisited vertex        */
 };
@@ -88,12 +94,12 @@ struct WView {
   uint64_t* vis;
   uint64_t* fr0;
   uint64_t* fr1;
-  int32_t* q0;
-  int32_t* q1;
+  int32_t* q0;          /* frontier queue of a top-down level            */
   int32_t* huge_u;
   uint32_t* huge_base;
-  int32_t* depth;
+  int32_t* depth;         /* caller's outputs (caller labels)              */
   int32_t* parent;
+  int64_t* packed;        /* relabelled graphs: internal (parent, depth)   */
   Ctl* ctl;
   dobfs_level_rec* log;
   int32_t log_cap;
@@ -105,7 +111,15 @@ hipError_t launch_init(const GView& g, const WView& w, int64_t root, int32_t fir
                        hipStream_t s);
 hipError_t launch_level(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s);
 hipError_t launch_aux(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s);
+hipError_t launch_finalize(const GView& g, const WView& w, int64_t root, int grid, hipStream_t s);
 hipError_t level_grid(int* grid);
+
+/* Degree relabelling (reindex.hip): builds the internal CSR of a graph whose
+   vertices are renumbered by degree, highest first (ties by caller ID),
+   every row sorted by internal ID, i.e. highest-degree neighbour first. */
+int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int grid, hipStream_t s,
+                    int64_t** off_new, int32_t** idx_new, int32_t** new2old, int32_t** old2new,
+                    std::string* err);
 
 /* Graph preparation launchers (graph_kernels.hip). */
 hipError_t launch_graph_scan(const int64_t* off, int64_t n, uint64_t* iso, int64_t* counters,

@@ -38,8 +38,24 @@ def _run(dobfs, dg, root, **kw):
     return d.cpu().numpy(), p.cpu().numpy(), st
 
 
-def _parity(dobfs, g, roots, params=None, replay=True, label=""):
-    with dobfs.Graph.upload(g.offsets, g.indices) as dg:
+def degree_relabel(g):
+    """The relabelling rule written out: internal ID = rank by degree,
+    highest first, ties by ID; rows sorted by internal ID."""
+    deg = g.degrees()
+    new2old = np.argsort(-deg, kind="stable")
+    old2new = np.empty_like(new2old)
+    old2new[new2old] = np.arange(g.n)
+    src = np.repeat(np.arange(g.n), deg)
+    key = np.sort(old2new[src].astype(np.int64) * g.n + old2new[g.indices])
+    off = np.zeros(g.n + 1, dtype=np.int64)
+    off[1:] = np.cumsum(deg[new2old])
+    return off, (key % g.n).astype(np.int32), new2old, old2new
+
+
+def _parity(dobfs, g, roots, params=None, replay=True, label="", reindex=False):
+    if reindex:
+        r_off, r_idx, new2old, _ = degree_relabel(g)
+    with dobfs.Graph.upload(g.offsets, g.indices, reindex=reindex) as dg:
         for r in roots:
             r = int(r)
             _say(f"[parity] {label or g.name} n={g.n} m={g.m} root={r}")
@@ -52,7 +68,10 @@ def _parity(dobfs, g, roots, params=None, replay=True, label=""):
             assert st.reached == int((exp >= 0).sum())
             assert st.levels == int(exp.max()) + 1
             if replay and len(st.log) == st.levels:
-                rep = oracle.replay(g.offsets, g.indices, exp, st.dirs())
+                if reindex:
+                    rep = oracle.replay(r_off, r_idx, exp[new2old], st.dirs())
+                else:
+                    rep = oracle.replay(g.offsets, g.indices, exp, st.dirs())
                 got = np.array([[rec["n_f"], rec["m_f"], rec["scanned"], rec["checked"], rec["found"],
                                  rec["found_deg"]] for rec in st.log])
                 assert np.array_equal(got, rep[:, :6]), (label, r, got, rep[:, :6])
@@ -175,3 +194,49 @@ def test_device_upload_and_errors(dobfs):
     idx2[-1] = 0  # row 2 becomes [0]: edge (2, 0) without (0, 2)
     with pytest.raises(dobfs.DobfsError):
         dobfs.Graph.upload(asym.offsets, idx2, check_symmetry=True)
+
+
+# ---------------------------------------------------------------------------
+# Degree-relabelled graphs: outputs in the caller's labels, work counters
+# equal to the replay over the relabelled CSR built by the rule above.
+
+def test_reindex_closed_forms(dobfs):
+    cases = [gg.path(50), gg.star(300), gg.complete_bipartite(3, 70), gg.grid2d(9, 11), gg.binary_tree(500),
+             gg.disjoint_union(gg.path(70), gg.cycle(9), gg.from_edges(3, [], [])), gg.from_edges(1, [], [])]
+    for g in cases:
+        roots = sorted({0, g.n // 2, g.n - 1})
+        for pol in ("edge", "td", "bu"):
+            _parity(dobfs, g, roots, params=dobfs.make_params(pol), label=f"{g.name}/{pol}/reindex", reindex=True)
+
+
+def test_reindex_kronecker_policies(dobfs):
+    g = gg.kronecker(15, seed=6)
+    roots = gg.sample_roots(g, 4, seed=8)
+    for pol in ("edge", "td", "bu", "paper"):
+        _parity(dobfs, g, roots, params=dobfs.make_params(pol), label=f"kron15/{pol}/reindex", reindex=True)
+    _parity(dobfs, g, roots[:2], params=dobfs.make_params("random", seed=3), label="kron15/random/reindex",
+            reindex=True)
+
+
+def test_reindex_kronecker_s16_sixteen_roots(dobfs):
+    g = gg.kronecker(16, seed=1)
+    roots = gg.sample_roots(g, 16, seed=1_000_001)
+    _parity(dobfs, g, roots, label="kron16/reindex", reindex=True)
+
+
+def test_reindex_device_source_and_parent_optional(dobfs):
+    import torch
+    g = gg.kronecker(12, seed=4)
+    off = torch.from_numpy(g.offsets).cuda()
+    idx = torch.from_numpy(g.indices).cuda()
+    r = int(gg.sample_roots(g, 1, seed=1)[0])
+    exp = oracle.bfs(g.offsets, g.indices, r)[0]
+    with dobfs.Graph.upload(off, idx, reindex=True) as dg:
+        info = dg.info()
+        assert info["flags"] & dobfs.REINDEX_DEGREE
+        assert info["n_nonisolated"] == int((g.degrees() > 0).sum())
+        d, p, _ = dg.run(r, want_parent=False)
+        torch.cuda.synchronize()
+        assert p is None and np.array_equal(d.cpu().numpy(), exp)
+    # the source arrays are left untouched
+    assert np.array_equal(off.cpu().numpy(), g.offsets) and np.array_equal(idx.cpu().numpy(), g.indices)
