@@ -49,6 +49,17 @@ def level_bytes(rec: dict, words_active: int) -> float:
     return (16.0 * words_active + 8.0 * rec["scanned"] + (4.0 + 0.125) * rec["checked"] + 8.0 * rec["found"])
 
 
+def kernel_source_digest() -> str:
+    """Identity of the level kernel's source: measured traffic is only
+    reported for the kernel it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("bfs_kernels.hip", "dobfs_internal.h"):
+        with open(os.path.join(ROOT, "paper_1503_04359_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def harmonic_mean(xs):
     return len(xs) / sum(1.0 / x for x in xs)
 
@@ -94,6 +105,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per level-kernel launch (rocprofv3 --pmc), if present")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="first run a plain device copy kernel over this many GiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -110,6 +123,16 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_probe > 0:
+        # elementwise copy kernel: reads and writes exactly `nbytes` each
+        nbytes = int(args.copy_probe * (1 << 30)) // 4 * 4
+        a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.add(a, 0, out=b)
+        torch.cuda.synchronize()
+        log(f"[gpu] copy probe: {nbytes} bytes read and written by one elementwise kernel")
+        del a, b
+        torch.cuda.empty_cache()
     t0 = time.time()
     g = gg.kronecker_device(args.scale, args.edgefactor, seed=args.seed)
     torch.cuda.synchronize()
@@ -176,12 +199,13 @@ def main() -> int:
         try:
             with open(args.traffic) as f:
                 tr = json.load(f)
-            key = f"kron-s{args.scale}-ef{args.edgefactor}-seed{args.seed}/{args.policy}"
-            if key in tr and tr[key].get("kernel") == "k_level":
-                traffic = tr[key]["bytes_per_launch"]
+            key = f"kron-s{args.scale}-ef{args.edgefactor}-seed{args.seed}/{args.policy}/reindex-{args.reindex}"
+            ent = tr.get(key, {})
+            if ent.get("kernel") == "k_level" and ent.get("source_sha256") == kernel_source_digest():
+                traffic = ent["bytes_per_launch"]
         except (OSError, ValueError):
             traffic = None
-    roofline = {"bound": "hbm", "kernel": "k_level", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    roofline = {"bound": "hbm", "kernel": "k_level", "source_sha256": kernel_source_digest()[:16], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": round(per_launch), "avg_launch_ms": round(avg_ms, 5),
                 "launches": tot_launch}

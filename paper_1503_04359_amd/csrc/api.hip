@@ -125,6 +125,10 @@ int alloc_workspace(dobfs_graph_s* g, Workspace* w) {
     return fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "workspace allocation", e);
   }
   w->log_cap = kLogCap;
+  if ((e = hipMemset(w->ctl, 0, sizeof(Ctl))) != hipSuccess) {  /* completion groups start at zero */
+    w->release();
+    return fail(DOBFS_EDEVICE, "workspace init", e);
+  }
   if ((e = hipHostMalloc(reinterpret_cast<void**>(&w->done_host), 2 * sizeof(int32_t))) != hipSuccess ||
       (e = hipEventCreateWithFlags(&w->ev[0], hipEventDisableTiming)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&w->ev[1], hipEventDisableTiming)) != hipSuccess ||

@@ -67,9 +67,20 @@ __device__ __forceinline__ int64_t wave_sum(int64_t x) {
   return x;
 }
 
-/* Per-workgroup reduction of the accumulators, one atomic per counter. */
-__device__ void flush_acc(Ctl* ctl, Acc a) {
+template <class T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+/* End of a workgroup's share of a level kernel: its accumulators are summed
+   and handed on, and the call returns true in thread 0 of the last
+   workgroup of the grid.  Workgroups report to one of kGroups group slots
+   (one cache line each) and the last of each group forwards the group's sums
+   to the level counters, so no address sees more than gridDim/kGroups
+   atomics. */
+__device__ bool finish_block(Ctl* c, Acc a) {
   __shared__ int64_t part[4][kBlock / kWave];
+  __shared__ int is_last;
   const int lane = lane_id(), wv = threadIdx.x / kWave;
   a.found = wave_sum(a.found);
   a.found_deg = wave_sum(a.found_deg);
@@ -83,33 +94,37 @@ __device__ void flush_acc(Ctl* ctl, Acc a) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int64_t s[4] = {0, 0, 0, 0};
+    int64_t sum[4] = {0, 0, 0, 0};
     for (int k = 0; k < 4; ++k)
-      for (int j = 0; j < kBlock / kWave; ++j) s[k] += part[k][j];
-    if (s[0]) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->nf_next), (unsigned long long)s[0]);
-    if (s[1]) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->mf_next), (unsigned long long)s[1]);
-    if (s[2]) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->checked), (unsigned long long)s[2]);
-    if (s[3]) atomicAdd(reinterpret_cast<unsigned long long*>(&ctl->scanned), (unsigned long long)s[3]);
-  }
-}
-
-/* Returns true in thread 0 of the last workgroup to pass this point. */
-__device__ bool last_block(Ctl* ctl) {
-  __shared__ int is_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
+      for (int j = 0; j < kBlock / kWave; ++j) sum[k] += part[k][j];
+    const uint32_t ng = gridDim.x < (uint32_t)kGroups ? gridDim.x : (uint32_t)kGroups;
+    const uint32_t grp = blockIdx.x % ng;
+    const uint32_t gsize = (gridDim.x - grp + ng - 1) / ng;
+    GroupSlot& gs = c->grp[grp];
+    for (int k = 0; k < 4; ++k)
+      if (sum[k]) atomicAdd(reinterpret_cast<unsigned long long*>(&gs.sum[k]), (unsigned long long)sum[k]);
     __threadfence();
-    const uint32_t t = atomicAdd(&ctl->ticket, 1u);
-    is_last = (t == gridDim.x - 1);
-    if (is_last) __threadfence();
+    bool last = false;
+    if (atomicAdd(&gs.ticket, 1u) == gsize - 1) {
+      __threadfence();
+      int64_t* tot[4] = {&c->nf_next, &c->mf_next, &c->checked, &c->scanned};
+      for (int k = 0; k < 4; ++k) {
+        const int64_t v = ld_agent(&gs.sum[k]);
+        gs.sum[k] = 0;
+        if (v) atomicAdd(reinterpret_cast<unsigned long long*>(tot[k]), (unsigned long long)v);
+      }
+      gs.ticket = 0;
+      __threadfence();
+      last = atomicAdd(&c->ticket, 1u) == ng - 1;
+      if (last) {
+        c->ticket = 0;
+        __threadfence();
+      }
+    }
+    is_last = last;
   }
   __syncthreads();
   return threadIdx.x == 0 && is_last;
-}
-
-template <class T>
-__device__ __forceinline__ T ld_agent(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int random_dir(uint64_t seed, int32_t level) {
@@ -124,7 +139,6 @@ __device__ __forceinline__ int random_dir(uint64_t seed, int32_t level) {
    rule and set up level L+1.  Runs in one thread. */
 __device__ void decide(const GView& g, const WView& w, const KParams& kp) {
   Ctl* c = w.ctl;
-  c->ticket = 0;
   const int32_t L = c->level;
   const int32_t dir = c->dir;
   const int64_t nfn = ld_agent(&c->nf_next);
@@ -290,14 +304,53 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
   }
 }
 
-/* Bottom-up level.  One wavefront per 64-vertex word.  The unvisited
-   vertices' adjacency lists are scanned in rounds: in round r each vertex
-   still searching contributes its next min(2^r, remaining) neighbours, the
-   contributions are laid end to end and cut into 64-entry chunks, and each
-   lane tests one neighbour of one chunk.  Every lane does useful work even
-   when degrees differ inside the word, neighbour IDs of one vertex are read
-   contiguously, and a vertex stops at the round in which it finds its first
-   frontier neighbour (its parent: the first hit in adjacency order). */
+/* Owner lane of concatenated position p (first lane whose inclusive end
+   exceeds p; incl is non-decreasing across lanes). */
+__device__ __forceinline__ int owner_of(int incl, int p) {
+  int lo = 0;
+  for (int step = kWave / 2; step > 0; step >>= 1)
+    if (__shfl(incl, lo + step - 1) <= p) lo += step;
+  return lo < kWave ? lo : kWave - 1;
+}
+
+/* One 64-entry chunk [c0, c0+64) of a bottom-up round: this lane's slice of
+   it is [max(excl,c0), min(incl,c0+64)); H marks the entries that hit the
+   frontier.  Records the first hit of the slice as the lane's parent. */
+__device__ __forceinline__ void resolve_chunk(uint64_t H, int c0, int excl, int incl, int take, int32_t u,
+                                              bool& found, int32_t& par, Acc& a) {
+  const int lane = lane_id();
+  const int sa = max(excl, c0) - c0, sb = min(incl, c0 + kWave) - c0;
+  int src = lane;
+  bool got = false;
+  if (take > 0 && sa < sb && !found) {
+    const uint64_t span = (sb - sa >= 64) ? ~0ull : (((1ull << (sb - sa)) - 1ull) << sa);
+    const uint64_t h = H & span;
+    if (h) {
+      src = __ffsll((unsigned long long)h) - 1;
+      got = true;
+      a.checked += src - sa + 1;
+    } else {
+      a.checked += sb - sa;
+    }
+  }
+  const int32_t pu = __shfl(u, src);
+  if (got) {
+    found = true;
+    par = pu;
+  }
+}
+
+/* Bottom-up level.  One wavefront per 64-vertex word.  Round 0: every
+   unvisited vertex tests its first neighbour (its highest-degree one on a
+   relabelled graph), one lane per vertex.  Later rounds: each vertex still
+   searching contributes its next min(2^r, remaining) neighbours, the
+   contributions are laid end to end and cut into 64-entry chunks (two
+   chunks in flight at a time), and each lane tests one neighbour.  Every
+   lane does useful work even when degrees differ inside the word, one
+   vertex's neighbour IDs are read contiguously, and a vertex stops at the
+   round in which it meets its first frontier neighbour (its parent: the
+   first hit in adjacency order).  The next word's visited bits are loaded
+   one iteration ahead. */
 __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int32_t L, Acc& a) {
   const uint64_t* f_cur = (L & 1) ? w.fr1 : w.fr0;
   uint64_t* f_nxt = (L & 1) ? w.fr0 : w.fr1;
@@ -305,9 +358,12 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const int max_quota = kp.bu_heavy_cut < kWave ? kWave : kp.bu_heavy_cut;
+  const int64_t W = g.words_active;
 
-  for (int64_t wd = wave; wd < g.words_active; wd += nwaves) {
-    const uint64_t vis = w.vis[wd];
+  uint64_t vis_next = wave < W ? w.vis[wave] : ~0ull;
+  for (int64_t wd = wave; wd < W; wd += nwaves) {
+    const uint64_t vis = vis_next;
+    if (wd + nwaves < W) vis_next = w.vis[wd + nwaves];
     if (vis == ~0ull) {
       if (lane == 0) f_nxt[wd] = 0ull;
       continue;
@@ -323,48 +379,35 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
     a.scanned += unv ? 1 : 0;
     bool found = false;
     int32_t par = -1;
-    int quota = 1;
+    /* round 0: own first neighbour */
+    if (pos < end) {
+      const int32_t u = g.idx[pos];
+      a.checked += 1;
+      if (test_bit(f_cur, u)) {
+        found = true;
+        par = u;
+      }
+      ++pos;
+    }
+    int quota = 2;
     while (__ballot(!found && pos < end)) {
       const int take = (!found && pos < end) ? (int)min(end - pos, (int64_t)quota) : 0;
       const int incl = wave_incl_scan(take, lane);
       const int excl = incl - take;
       const int total = __shfl(incl, kWave - 1);
-      for (int c0 = 0; c0 < total; c0 += kWave) {
-        /* owner of concatenated position p: first lane whose incl > p */
-        const int p = c0 + lane;
-        int lo = 0;  /* lanes with incl <= p (incl is non-decreasing) */
-        for (int step = kWave / 2; step > 0; step >>= 1)
-          if (__shfl(incl, lo + step - 1) <= p) lo += step;
-        const int o = lo < kWave ? lo : kWave - 1;
-        const int64_t opos = __shfl(pos, o);
-        const int oexcl = __shfl(excl, o);
-        int32_t u = 0;
-        bool hit = false;
-        if (p < total) {
-          u = g.idx[opos + (p - oexcl)];
-          hit = test_bit(f_cur, u);
-        }
-        const uint64_t H = __ballot(hit);
-        /* this lane's slice of the chunk: [sa, sb) */
-        const int sa = max(excl, c0) - c0, sb = min(incl, c0 + kWave) - c0;
-        int src = lane;
-        bool got = false;
-        if (take > 0 && sa < sb && !found) {
-          const uint64_t span = (sb - sa >= 64) ? ~0ull : (((1ull << (sb - sa)) - 1ull) << sa);
-          const uint64_t h = H & span;
-          if (h) {
-            src = __ffsll((unsigned long long)h) - 1;
-            got = true;
-            a.checked += src - sa + 1;
-          } else {
-            a.checked += sb - sa;
-          }
-        }
-        const int32_t pu = __shfl(u, src);
-        if (got) {
-          found = true;
-          par = pu;
-        }
+      for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
+        const int p1 = c0 + lane, p2 = c0 + kWave + lane;
+        const int o1 = owner_of(incl, p1), o2 = owner_of(incl, p2);
+        const int64_t e1 = __shfl(pos, o1) + (p1 - __shfl(excl, o1));
+        const int64_t e2 = __shfl(pos, o2) + (p2 - __shfl(excl, o2));
+        int32_t u1 = 0, u2 = 0;
+        if (p1 < total) u1 = g.idx[e1];
+        if (p2 < total) u2 = g.idx[e2];
+        const bool h1 = p1 < total && test_bit(f_cur, u1);
+        const bool h2 = p2 < total && test_bit(f_cur, u2);
+        const uint64_t H1 = __ballot(h1), H2 = __ballot(h2);
+        resolve_chunk(H1, c0, excl, incl, take, u1, found, par, a);
+        resolve_chunk(H2, c0 + kWave, excl, incl, take, u2, found, par, a);
       }
       pos += take;
       if (quota < max_quota) quota <<= 1;
@@ -382,7 +425,7 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_level(GView g, WView w, KParams kp) {
+__global__ void __launch_bounds__(kBlock, 8) k_level(GView g, WView w, KParams kp) {
   Ctl* c = w.ctl;
   if (c->done || c->aux != kAuxNone) return;
   const int32_t L = c->level;
@@ -390,10 +433,8 @@ __global__ void __launch_bounds__(kBlock) k_level(GView g, WView w, KParams kp) 
   Acc a = {0, 0, 0, 0};
   if (dir == kDirTD) top_down(g, w, kp, L, a);
   else bottom_up(g, w, kp, L, a);
-  flush_acc(c, a);
-  if (last_block(c)) {
+  if (finish_block(c, a)) {
     if (dir == kDirTD && ld_agent(&c->huge_pack) != 0ull) {
-      c->ticket = 0;
       c->aux = kAuxHuge;
     } else {
       decide(g, w, kp);
@@ -463,8 +504,7 @@ __global__ void __launch_bounds__(kBlock) k_aux(GView g, WView w, KParams kp) {
         if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, u, L, a);
       }
     }
-    flush_acc(c, a);
-    if (last_block(c)) {
+    if (finish_block(c, a)) {
       c->aux = kAuxNone;
       decide(g, w, kp);
     }
@@ -509,19 +549,14 @@ __global__ void __launch_bounds__(kBlock) k_aux(GView g, WView w, KParams kp) {
       run += chunk_total;
     }
   }
-  if (last_block(c)) {
-    c->ticket = 0;
-    c->aux = kAuxNone;
-  }
+  const Acc none = {0, 0, 0, 0};
+  if (finish_block(c, none)) c->aux = kAuxNone;
 }
 
 __global__ void __launch_bounds__(kBlock) k_init_fill(GView g, WView w) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-  if (w.packed) {
-    /* internal labels: only non-isolated vertices can be reached */
-    for (int64_t i = tid; i < g.n_nonisolated; i += nth) w.packed[i] = -1;
-  } else {
+  if (!w.packed) {  /* relabelled graphs: the finalize kernel reads the visited bitmap instead */
     for (int64_t i = tid; i < g.n; i += nth) {
       w.depth[i] = -1;
       w.parent[i] = -1;
@@ -561,7 +596,6 @@ __global__ void k_init_root(GView g, WView w, int32_t root_caller, int32_t first
   c->scanned = 0;
   c->huge_pack = 0ull;
   c->q_fill = 0;
-  c->ticket = 0;
   c->reached = 1;
   c->reached_deg = dr;
   c->checked_total = 0;
@@ -569,16 +603,16 @@ __global__ void k_init_root(GView g, WView w, int32_t root_caller, int32_t first
 }
 
 /* Relabelled graphs: caller-label outputs from the packed internal words.
-   Caller vertex x has internal label old2new[x]; internal labels at or
-   beyond n_nonisolated have degree 0 and are unreached unless x is the
-   root. */
+   Caller vertex x has internal label v = old2new[x]; v was reached exactly
+   when it is the root or its visited bit is set and v < n_nonisolated
+   (degree-0 vertices start visited but are never reached). */
 __global__ void __launch_bounds__(kBlock) k_finalize(GView g, WView w, int32_t root_caller) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   for (int64_t x = tid; x < g.n; x += nth) {
     const int32_t v = g.old2new[x];
     int32_t d = -1, p = -1;
-    if ((int64_t)v < g.n_nonisolated || x == root_caller) {
+    if (x == root_caller || ((int64_t)v < g.n_nonisolated && ((w.vis[v >> 6] >> (v & 63)) & 1ull))) {
       const uint64_t rec = (uint64_t)w.packed[v];
       d = (int32_t)(uint32_t)(rec & 0xFFFFFFFFull);
       const int32_t pn = (int32_t)(uint32_t)(rec >> 32);

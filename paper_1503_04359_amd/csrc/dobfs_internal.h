@@ -44,6 +44,14 @@ constexpr int kAuxNone = 0;
 constexpr int kAuxHuge = 1;          /* split top-down vertices still to expand */
 constexpr int kAuxToQueue = 2;       /* next level top-down: bitmap to queue */
 
+constexpr int kGroups = 16;          /* completion groups per kernel (see finish_block) */
+
+struct GroupSlot {
+  int64_t sum[4];
+  uint32_t ticket;
+  uint32_t pad[23];     /* one 128-byte cache line per group */
+};
+
 /* Level state, advanced on the device by the last workgroup of each level. */
 struct Ctl {
   int32_t level;        /* L: frontier = vertices of depth L              */
@@ -69,6 +77,7 @@ struct Ctl {
   /* totals */
   int64_t reached, reached_deg, checked_total;
   uint64_t t_begin;
+  GroupSlot grp[kGroups]; /* zero between kernels */
 };
 
 struct KParams {

@@ -47,42 +47,50 @@ __global__ void __launch_bounds__(kBlock) k_graph_scan(const int64_t* off, int64
 
 /* bad[0]: first problem found (0 none, 1 offsets, 2 index range,
    3 self-loop, 4 missing reverse edge). */
-__global__ void __launch_bounds__(kBlock) k_validate(const int64_t* off, const int32_t* idx, int64_t n,
-                                                   int64_t m, int symmetry, int32_t* bad) {
+__global__ void __launch_bounds__(kBlock) k_validate_offsets(const int64_t* off, int64_t n, int64_t m, int32_t* bad) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   if (tid == 0 && (off[0] != 0 || off[n] != m)) atomicCAS(bad, 0, 1);
   for (int64_t v = tid; v < n; v += nth) {
     const int64_t b = off[v], e = off[v + 1];
-    if (b > e || b < 0 || e > m) {
-      atomicCAS(bad, 0, 1);
-      continue;
-    }
-    for (int64_t k = b; k < e; ++k) {
+    if (b > e || b < 0 || e > m) atomicCAS(bad, 0, 1);
+  }
+}
+
+/* Every neighbour ID in [0, n); run only once the offsets passed. */
+__global__ void __launch_bounds__(kBlock) k_validate_indices(const int32_t* idx, int64_t n, int64_t m,
+                                                           const int32_t* bad_in, int32_t* bad) {
+  if (*bad_in) return;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += nth) {
+    const int32_t u = idx[e];
+    if (u < 0 || (int64_t)u >= n) atomicCAS(bad, 0, 2);
+  }
+}
+
+/* No self-loop and every (v, u) has (u, v); rows sorted ascending. */
+__global__ void __launch_bounds__(kBlock) k_validate_symmetry(const int64_t* off, const int32_t* idx, int64_t n,
+                                                            int32_t* bad) {
+  if (*bad) return;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += nth) {
+    for (int64_t k = off[v]; k < off[v + 1]; ++k) {
       const int32_t u = idx[k];
-      if (u < 0 || (int64_t)u >= n) {
-        atomicCAS(bad, 0, 2);
-        break;
-      }
       if ((int64_t)u == v) {
         atomicCAS(bad, 0, 3);
         break;
       }
-      if (symmetry) {
-        int64_t lo = off[u], hi = off[u + 1];
-        bool ok = false;
-        if (lo >= 0 && hi <= m && lo <= hi) {
-          while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            const int32_t x = idx[mid];
-            if (x == (int32_t)v) { ok = true; break; }
-            if (x < (int32_t)v) lo = mid + 1; else hi = mid;
-          }
-        }
-        if (!ok) {
-          atomicCAS(bad, 0, 4);
-          break;
-        }
+      int64_t lo = off[u], hi = off[u + 1];
+      bool ok = false;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const int32_t x = idx[mid];
+        if (x == (int32_t)v) { ok = true; break; }
+        if (x < (int32_t)v) lo = mid + 1; else hi = mid;
+      }
+      if (!ok) {
+        atomicCAS(bad, 0, 4);
+        break;
       }
     }
   }
@@ -98,7 +106,9 @@ hipError_t launch_graph_scan(const int64_t* off, int64_t n, uint64_t* iso, int64
 
 hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int symmetry,
                            int32_t* bad, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_validate, dim3(grid), dim3(kBlock), 0, s, off, idx, n, m, symmetry, bad);
+  hipLaunchKernelGGL(k_validate_offsets, dim3(grid), dim3(kBlock), 0, s, off, n, m, bad);
+  hipLaunchKernelGGL(k_validate_indices, dim3(grid), dim3(kBlock), 0, s, idx, n, m, bad, bad);
+  if (symmetry) hipLaunchKernelGGL(k_validate_symmetry, dim3(grid), dim3(kBlock), 0, s, off, idx, n, bad);
   return hipGetLastError();
 }
 

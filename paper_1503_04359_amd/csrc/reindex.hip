@@ -2,16 +2,20 @@
  * Degree relabelling of a resident graph (locality optimisation of Section
  * 3.4, rethought for one GPU).
  *
- * Internal ID = rank of the vertex by degree, highest first, ties by caller
- * ID; every adjacency list is rewritten in internal IDs and sorted
- * ascending, which puts the highest-degree neighbour first (the order the
+ * Internal ID = rank of the vertex by degree class, highest first, ties by
+ * caller ID.  The degree class of d >= 1 is 2*bitlength(d) + (the bit below
+ * the leading one), i.e. two classes per power of two; degree 0 is class 0.
+ * Every adjacency list is rewritten in internal IDs and sorted ascending,
+ * which puts neighbours of the highest degree class first (the order the
  * paper uses so that bottom-up scans stop early).  On the device this also
  *   - gathers the hubs into a short ID prefix, so the frontier-bitmap words
  *     probed most often stay in L2,
  *   - makes the vertices of one 64-vertex word similar in degree,
  *   - puts every degree-0 vertex in a suffix that bottom-up steps never
- *     visit.
- * Steps: stable radix sort of (max_deg - degree, ID) -> new2old; inverse ->
+ *     visit,
+ *   - keeps caller order inside each class, so mapping results back to
+ *     caller IDs reads ~64 sequential streams instead of random words.
+ * Steps: stable radix sort of (max_class - class, ID) -> new2old; inverse ->
  * old2new; scan of permuted degrees -> offsets; rows copied and mapped
  * (short rows one wavefront each, rows above kLongRow cut into chunks spread
  * over all wavefronts); rows sorted in bounded batches with a segmented
@@ -46,10 +50,18 @@ __device__ __forceinline__ int lane_of() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
 }
 
-__global__ void k_sort_keys(const int64_t* off, int64_t n, uint32_t max_deg, uint32_t* keys, int32_t* ids) {
+__host__ __device__ inline uint32_t degree_class(int64_t d) {
+  if (d <= 0) return 0u;
+  int bl = 0;
+  while (bl < 63 && ((int64_t)1 << bl) <= d) ++bl;  /* bit length */
+  const uint32_t below = bl >= 2 ? (uint32_t)((d >> (bl - 2)) & 1) : 0u;
+  return 2u * (uint32_t)bl + below;
+}
+
+__global__ void k_sort_keys(const int64_t* off, int64_t n, uint32_t max_class, uint32_t* keys, int32_t* ids) {
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += nth) {
-    keys[v] = max_deg - (uint32_t)(off[v + 1] - off[v]);
+    keys[v] = max_class - degree_class(off[v + 1] - off[v]);
     ids[v] = (int32_t)v;
   }
 }
@@ -190,10 +202,11 @@ int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m
   int64_t max_deg = 0;
   RX(hipMemcpyAsync(&max_deg, d_max, sizeof(int64_t), hipMemcpyDeviceToHost, s), "max copy");
   RX(hipStreamSynchronize(s), "max sync");
+  const uint32_t max_class = degree_class(max_deg);
   int bits = 1;
-  while (bits < 32 && ((int64_t)1 << bits) <= max_deg) ++bits;
+  while (bits < 32 && ((uint32_t)1 << bits) <= max_class) ++bits;
 
-  /* new2old: stable sort by (max_deg - degree) over ascending IDs */
+  /* new2old: stable sort by (max_class - class) over ascending IDs */
   RX(hipMalloc(&new2old, sizeof(int32_t) * (size_t)n), "new2old");
   {
     uint32_t *k_in = nullptr, *k_out = nullptr;
@@ -201,7 +214,7 @@ int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m
     RX(tmp.get(&k_in, n), "sort keys");
     RX(tmp.get(&k_out, n), "sort keys");
     RX(tmp.get(&v_in, n), "sort ids");
-    hipLaunchKernelGGL(k_sort_keys, dim3(grid), dim3(kBlock), 0, s, off, n, (uint32_t)max_deg, k_in, v_in);
+    hipLaunchKernelGGL(k_sort_keys, dim3(grid), dim3(kBlock), 0, s, off, n, max_class, k_in, v_in);
     RX(hipGetLastError(), "keys");
     size_t bytes = 0;
     RX(rocprim::radix_sort_pairs(nullptr, bytes, k_in, k_out, v_in, new2old, (size_t)n, 0u, (unsigned)bits, s),
@@ -242,16 +255,15 @@ int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m
 
   /* rows copied in internal IDs */
   RX(hipMalloc(&idx_new, sizeof(int32_t) * (size_t)(m > 0 ? m : 1)), "indices");
-  int64_t r_long = 0;  /* rows longer than kLongRow form a prefix */
+  int64_t r_long = 0;  /* rows of a class above kLongRow's form a prefix; all longer than kCopyChunk */
   {
+    const uint32_t long_class = degree_class(kLongRow);  /* classes above it have degree > kLongRow */
     int64_t lo = 0, hi = n;
-    /* degrees are non-increasing in internal order: find the first row with
-       degree <= kLongRow by bisection on the host over device reads */
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
       int64_t o2[2];
       RX(hipMemcpy(o2, off_new + mid, sizeof(o2), hipMemcpyDeviceToHost), "bisect");
-      if (o2[1] - o2[0] > kLongRow) lo = mid + 1; else hi = mid;
+      if (degree_class(o2[1] - o2[0]) > long_class) lo = mid + 1; else hi = mid;
     }
     r_long = lo;
   }
@@ -266,8 +278,8 @@ int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m
   RX(hipStreamSynchronize(s), "copy sync");
 
   /* rows sorted by internal ID, in batches of whole rows bounded in both
-     entries and rows.  Rows of degree <= 1 (a suffix, since degrees are
-     non-increasing) need no sorting. */
+     entries and rows.  Rows of degree <= 1 (classes 0 and 2, a suffix)
+     need no sorting. */
   int64_t n_sort = 0;
   {
     int64_t lo = 0, hi = n;
@@ -275,7 +287,7 @@ int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m
       const int64_t mid = (lo + hi) >> 1;
       int64_t o2[2];
       RX(hipMemcpy(o2, off_new + mid, sizeof(o2), hipMemcpyDeviceToHost), "bisect");
-      if (o2[1] - o2[0] >= 2) lo = mid + 1; else hi = mid;
+      if (degree_class(o2[1] - o2[0]) > degree_class(1)) lo = mid + 1; else hi = mid;
     }
     n_sort = lo;
   }

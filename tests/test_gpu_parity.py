@@ -38,11 +38,22 @@ def _run(dobfs, dg, root, **kw):
     return d.cpu().numpy(), p.cpu().numpy(), st
 
 
+def degree_class(d):
+    """Two classes per power of two: 2 * bit length + the bit below the
+    leading one; degree 0 is class 0."""
+    d = np.asarray(d, dtype=np.int64)
+    bl = np.zeros_like(d)
+    nz = d > 0
+    bl[nz] = np.floor(np.log2(d[nz])).astype(np.int64) + 1
+    below = np.where(bl >= 2, (d >> np.maximum(bl - 2, 0)) & 1, 0)
+    return np.where(nz, 2 * bl + below, 0)
+
+
 def degree_relabel(g):
-    """The relabelling rule written out: internal ID = rank by degree,
+    """The relabelling rule written out: internal ID = rank by degree class,
     highest first, ties by ID; rows sorted by internal ID."""
     deg = g.degrees()
-    new2old = np.argsort(-deg, kind="stable")
+    new2old = np.lexsort((np.arange(g.n), -degree_class(deg)))
     old2new = np.empty_like(new2old)
     old2new[new2old] = np.arange(g.n)
     src = np.repeat(np.arange(g.n), deg)
