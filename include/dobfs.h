@@ -81,6 +81,13 @@ typedef struct dobfs_graph_s* dobfs_graph_t; /* opaque, library-owned */
 #define DOBFS_POLICY_FORCED_BU 3 /* every level bottom-up                     */
 #define DOBFS_POLICY_RANDOM 4    /* direction of level L = bit of a hash of
                                     (seed, L); for testing invariance        */
+#define DOBFS_POLICY_COST 5      /* top-down -> bottom-up when the next
+                                    frontier's edges exceed kappa/1000 times
+                                    the unvisited vertices of degree >= 1
+                                    (the work each direction would do on a
+                                    GPU, where bottom-up cost follows the
+                                    vertices scanned); back to top-down as
+                                    for EDGE                                */
 
 typedef struct {
   int32_t policy;          /* DOBFS_POLICY_*                                */
@@ -98,6 +105,7 @@ typedef struct {
                               one vertex cooperatively (default 256)        */
   int32_t chunk_levels;    /* levels enqueued per host check (default 8)    */
   uint32_t flags;          /* DOBFS_RUN_* (default 0)                       */
+  int32_t kappa_x1000;     /* COST, default 500                             */
   uint64_t seed;           /* RANDOM policy                                 */
 } dobfs_params;
 

@@ -28,9 +28,9 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 SRC_DEVICE, VALIDATE, VALIDATE_SYMMETRY, REINDEX_DEGREE, BORROW = 0x1, 0x2, 0x4, 0x8, 0x10
 RUN_TIME_KERNELS = 0x1
-POLICY_EDGE, POLICY_PAPER, POLICY_FORCED_TD, POLICY_FORCED_BU, POLICY_RANDOM = 0, 1, 2, 3, 4
+POLICY_EDGE, POLICY_PAPER, POLICY_FORCED_TD, POLICY_FORCED_BU, POLICY_RANDOM, POLICY_COST = 0, 1, 2, 3, 4, 5
 POLICIES = {"edge": POLICY_EDGE, "paper": POLICY_PAPER, "td": POLICY_FORCED_TD,
-            "bu": POLICY_FORCED_BU, "random": POLICY_RANDOM}
+            "bu": POLICY_FORCED_BU, "random": POLICY_RANDOM, "cost": POLICY_COST}
 
 EXPORTED = ("dobfs_default_params", "dobfs_graph_upload", "dobfs_graph_free", "dobfs_graph_info",
             "dobfs_run", "dobfs_strerror", "dobfs_last_error")
@@ -49,7 +49,8 @@ class CParams(ctypes.Structure):
                 ("paper_pct", ctypes.c_int32), ("paper_div", ctypes.c_int32),
                 ("paper_bu_steps", ctypes.c_int32), ("td_wave_cut", ctypes.c_int32),
                 ("td_huge_cut", ctypes.c_int32), ("bu_heavy_cut", ctypes.c_int32),
-                ("chunk_levels", ctypes.c_int32), ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+                ("chunk_levels", ctypes.c_int32), ("flags", ctypes.c_uint32), ("kappa_x1000", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
 
 
 class LevelRec(ctypes.Structure):

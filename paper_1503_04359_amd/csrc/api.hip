@@ -90,6 +90,8 @@ struct dobfs_graph_s {
   uint64_t* iso = nullptr;
   int32_t* new2old = nullptr;  /* relabelled graphs only */
   int32_t* old2new = nullptr;
+  int64_t* seg_lo = nullptr;
+  int32_t nseg = 0;
   int device = 0;
   int grid = 0;
   std::mutex mu;
@@ -102,6 +104,9 @@ struct dobfs_graph_s {
     g.iso = iso;
     g.old2new = old2new;
     g.new2old = new2old;
+    g.seg_lo = seg_lo;
+    g.nseg = nseg;
+    g.pad_seg = 0;
     g.n = n;
     g.m = m;
     g.n_nonisolated = n_nonisolated;
@@ -178,14 +183,14 @@ KParams to_kparams(const dobfs_params& p) {
   k.td_wave_cut = p.td_wave_cut;
   k.td_huge_cut = p.td_huge_cut < kMinHugeCut ? kMinHugeCut : p.td_huge_cut;
   k.bu_heavy_cut = p.bu_heavy_cut;
-  k.pad = 0;
+  k.kappa_x1000 = p.kappa_x1000;
   k.seed = p.seed;
   return k;
 }
 
 int check_params(const dobfs_params& p) {
-  if (p.policy < DOBFS_POLICY_EDGE || p.policy > DOBFS_POLICY_RANDOM) return fail(DOBFS_EINVAL, "unknown policy");
-  if (p.alpha < 1 || p.beta < 1 || p.paper_pct < 1 || p.paper_div < 1 || p.paper_bu_steps < 1)
+  if (p.policy < DOBFS_POLICY_EDGE || p.policy > DOBFS_POLICY_COST) return fail(DOBFS_EINVAL, "unknown policy");
+  if (p.alpha < 1 || p.beta < 1 || p.paper_pct < 1 || p.paper_div < 1 || p.paper_bu_steps < 1 || p.kappa_x1000 < 1)
     return fail(DOBFS_EINVAL, "switching constants must be >= 1");
   if (p.td_wave_cut < 0 || p.td_wave_cut > 4096 || p.td_huge_cut < 1 || p.bu_heavy_cut < 1)
     return fail(DOBFS_EINVAL, "degree cut-offs out of range");
@@ -224,6 +229,7 @@ void dobfs_default_params(dobfs_params* p) {
   p->bu_heavy_cut = 256;
   p->chunk_levels = 8;
   p->flags = 0;
+  p->kappa_x1000 = 500;
   p->seed = 0;
 }
 
@@ -276,6 +282,7 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
       dfree(g->iso);
       dfree(g->new2old);
       dfree(g->old2new);
+      dfree(g->seg_lo);
       delete g;
     }
     return status;
@@ -344,7 +351,8 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
   }
   if (reindex) {
     std::string err;
-    st = build_reindexed(src_off, src_idx, n, m, g->grid, s, &g->off, &g->idx, &g->new2old, &g->old2new, &err);
+    st = build_reindexed(src_off, src_idx, n, m, g->grid, s, &g->off, &g->idx, &g->new2old, &g->old2new,
+                         &g->seg_lo, &g->nseg, &err);
     drop_tmp();
     if (st != DOBFS_OK) return cleanup(fail(st, err.c_str()));
   }
@@ -380,6 +388,7 @@ int dobfs_graph_free(dobfs_graph_t g) {
   dfree(g->iso);
   dfree(g->new2old);
   dfree(g->old2new);
+  dfree(g->seg_lo);
   delete g;
   return DOBFS_OK;
 }

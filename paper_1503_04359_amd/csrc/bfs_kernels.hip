@@ -184,6 +184,12 @@ __device__ void decide(const GView& g, const WView& w, const KParams& kp) {
         else
           next = (bu_run >= kp.paper_bu_steps) ? kDirTD : kDirBU;
         break;
+      case DOBFS_POLICY_COST: {
+        const int64_t unvisited = g.n_nonisolated - (c->reached + nfn);
+        if (dir == kDirTD) next = (mfn * 1000 > (int64_t)kp.kappa_x1000 * unvisited) ? kDirBU : kDirTD;
+        else next = (nfn < c->n_f && nfn * (int64_t)kp.beta < g.n) ? kDirTD : kDirBU;
+        break;
+      }
       case DOBFS_POLICY_FORCED_TD: next = kDirTD; break;
       case DOBFS_POLICY_FORCED_BU: next = kDirBU; break;
       default: next = random_dir(kp.seed, L + 1); break;
@@ -605,18 +611,20 @@ __global__ void k_init_root(GView g, WView w, int32_t root_caller, int32_t first
 /* Relabelled graphs: caller-label outputs from the packed internal words.
    Caller vertex x has internal label v = old2new[x]; v was reached exactly
    when it is the root or its visited bit is set and v < n_nonisolated
-   (degree-0 vertices start visited but are never reached). */
+   (degree-0 vertices start visited but are never reached).  Parents are
+   mapped back through new2old. */
 __global__ void __launch_bounds__(kBlock) k_finalize(GView g, WView w, int32_t root_caller) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = tid; x < g.n; x += nth) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < g.n; x += nth) {
     const int32_t v = g.old2new[x];
     int32_t d = -1, p = -1;
-    if (x == root_caller || ((int64_t)v < g.n_nonisolated && ((w.vis[v >> 6] >> (v & 63)) & 1ull))) {
+    if (x == root_caller) {
+      d = 0;
+      p = root_caller;
+    } else if ((int64_t)v < g.n_nonisolated && ((w.vis[v >> 6] >> (v & 63)) & 1ull)) {
       const uint64_t rec = (uint64_t)w.packed[v];
       d = (int32_t)(uint32_t)(rec & 0xFFFFFFFFull);
-      const int32_t pn = (int32_t)(uint32_t)(rec >> 32);
-      p = pn >= 0 ? g.new2old[pn] : -1;
+      p = g.new2old[(int32_t)(uint32_t)(rec >> 32)];
     }
     w.depth[x] = d;
     if (w.parent) w.parent[x] = p;
@@ -651,7 +659,8 @@ hipError_t launch_level(const GView& g, const WView& w, const KParams& kp, int g
 }
 
 hipError_t launch_finalize(const GView& g, const WView& w, int64_t root, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kBlock), 0, s, g, w, (int32_t)root);
+  const int64_t blocks = grid;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(kBlock), 0, s, g, w, (int32_t)root);
   return hipGetLastError();
 }
 

@@ -44,7 +44,10 @@ constexpr int kAuxNone = 0;
 constexpr int kAuxHuge = 1;          /* split top-down vertices still to expand */
 constexpr int kAuxToQueue = 2;       /* next level top-down: bitmap to queue */
 
-constexpr int kGroups = 16;          /* completion groups per kernel (see finish_block) */
+constexpr int kGroups = 16;
+constexpr int kMaxSeg = 72;          /* degree classes of int64 degrees, plus one */
+constexpr int kFinBlock = 4096;      /* minimum caller IDs per finalize workgroup */
+constexpr int kFinGrid = 1024;       /* finalize workgroups (4 per CU) */          /* completion groups per kernel (see finish_block) */
 
 struct GroupSlot {
   int64_t sum[4];
@@ -83,7 +86,7 @@ struct Ctl {
 struct KParams {
   int32_t policy, alpha, beta, paper_pct, paper_div, paper_bu_steps;
   int32_t td_wave_cut, td_huge_cut, bu_heavy_cut;
-  int32_t pad;
+  int32_t kappa_x1000;
   uint64_t seed;
 };
 
@@ -93,6 +96,10 @@ struct GView {
   const uint64_t* iso;
   const int32_t* old2new;  /* relabelled graphs: caller ID -> internal ID  */
   const int32_t* new2old;  /* relabelled graphs: internal ID -> caller ID  */
+  const int64_t* seg_lo;   /* relabelled graphs: internal start of each degree
+                              class, ascending, seg_lo[nseg] = n           */
+  int32_t nseg;
+  int32_t pad_seg;
   int64_t n, m;
   int64_t n_nonisolated;
   int64_t words;         /* ceil(n/64)                                     */
@@ -128,7 +135,7 @@ hipError_t level_grid(int* grid);
    every row sorted by internal ID, i.e. highest-degree neighbour first. */
 int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int grid, hipStream_t s,
                     int64_t** off_new, int32_t** idx_new, int32_t** new2old, int32_t** old2new,
-                    std::string* err);
+                    int64_t** seg_lo, int32_t* nseg, std::string* err);
 
 /* Graph preparation launchers (graph_kernels.hip). */
 hipError_t launch_graph_scan(const int64_t* off, int64_t n, uint64_t* iso, int64_t* counters,

@@ -3,8 +3,8 @@
  * 3.4, rethought for one GPU).
  *
  * Internal ID = rank of the vertex by degree class, highest first, ties by
- * caller ID.  The degree class of d >= 1 is 2*bitlength(d) + (the bit below
- * the leading one), i.e. two classes per power of two; degree 0 is class 0.
+ * caller ID.  The degree class of d >= 1 is its bit length (one class per
+ * power of two); degree 0 is class 0.
  * Every adjacency list is rewritten in internal IDs and sorted ascending,
  * which puts neighbours of the highest degree class first (the order the
  * paper uses so that bottom-up scans stop early).  On the device this also
@@ -14,7 +14,8 @@
  *   - puts every degree-0 vertex in a suffix that bottom-up steps never
  *     visit,
  *   - keeps caller order inside each class, so mapping results back to
- *     caller IDs reads ~64 sequential streams instead of random words.
+ *     caller IDs reads a few dozen sequential streams instead of random
+ *     words.
  * Steps: stable radix sort of (max_class - class, ID) -> new2old; inverse ->
  * old2new; scan of permuted degrees -> offsets; rows copied and mapped
  * (short rows one wavefront each, rows above kLongRow cut into chunks spread
@@ -54,8 +55,7 @@ __host__ __device__ inline uint32_t degree_class(int64_t d) {
   if (d <= 0) return 0u;
   int bl = 0;
   while (bl < 63 && ((int64_t)1 << bl) <= d) ++bl;  /* bit length */
-  const uint32_t below = bl >= 2 ? (uint32_t)((d >> (bl - 2)) & 1) : 0u;
-  return 2u * (uint32_t)bl + below;
+  return (uint32_t)bl;
 }
 
 __global__ void k_sort_keys(const int64_t* off, int64_t n, uint32_t max_class, uint32_t* keys, int32_t* ids) {
@@ -119,6 +119,18 @@ __global__ void k_copy_long(const int64_t* off, const int32_t* idx, const int64_
   }
 }
 
+/* Internal IDs where the degree class changes (classes are non-increasing
+   along internal IDs, so each class is one contiguous range). */
+__global__ void k_class_bounds(const int64_t* off_new, int64_t n, int32_t* count, int64_t* out, int cap) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += nth) {
+    if (degree_class(off_new[v + 1] - off_new[v]) != degree_class(off_new[v] - off_new[v - 1])) {
+      const int k = atomicAdd(count, 1);
+      if (k < cap) out[k] = v;
+    }
+  }
+}
+
 __global__ void k_rel_offsets(const int64_t* off, int64_t r0, int64_t rows, uint32_t* rel) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i <= rows) rel[i] = (uint32_t)(off[r0 + i] - off[r0]);
@@ -166,8 +178,9 @@ int status_of(hipError_t e) { return e == hipErrorOutOfMemory ? DOBFS_ENOMEM : D
 
 int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int grid, hipStream_t s,
                     int64_t** off_new_out, int32_t** idx_new_out, int32_t** new2old_out, int32_t** old2new_out,
-                    std::string* err) {
+                    int64_t** seg_lo_out, int32_t* nseg_out, std::string* err) {
   Bufs tmp;
+  int64_t* seg_lo = nullptr;
   int64_t* off_new = nullptr;
   int32_t* idx_new = nullptr;
   int32_t* new2old = nullptr;
@@ -178,6 +191,7 @@ int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m
     (void)hipFree(idx_new);
     (void)hipFree(new2old);
     (void)hipFree(old2new);
+    (void)hipFree(seg_lo);
     return status_of(e);
   };
 #define RX(call, what)                        \
@@ -257,7 +271,7 @@ int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m
   RX(hipMalloc(&idx_new, sizeof(int32_t) * (size_t)(m > 0 ? m : 1)), "indices");
   int64_t r_long = 0;  /* rows of a class above kLongRow's form a prefix; all longer than kCopyChunk */
   {
-    const uint32_t long_class = degree_class(kLongRow);  /* classes above it have degree > kLongRow */
+    const uint32_t long_class = degree_class(kLongRow);  /* classes above it have degree >= 2 * kLongRow */
     int64_t lo = 0, hi = n;
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
@@ -278,7 +292,7 @@ int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m
   RX(hipStreamSynchronize(s), "copy sync");
 
   /* rows sorted by internal ID, in batches of whole rows bounded in both
-     entries and rows.  Rows of degree <= 1 (classes 0 and 2, a suffix)
+     entries and rows.  Rows of degree <= 1 (classes 0 and 1, a suffix)
      need no sorting. */
   int64_t n_sort = 0;
   {
@@ -346,6 +360,28 @@ int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m
     }
     RX(hipStreamSynchronize(s), "sort sync");
   }
+  /* degree-class segments of the internal ID space */
+  {
+    int32_t* d_cnt = nullptr;
+    int64_t* d_b = nullptr;
+    RX(tmp.get(&d_cnt, 1), "class bounds");
+    RX(tmp.get(&d_b, kMaxSeg), "class bounds");
+    RX(hipMemsetAsync(d_cnt, 0, sizeof(int32_t), s), "class bounds");
+    hipLaunchKernelGGL(k_class_bounds, dim3(grid), dim3(kBlock), 0, s, off_new, n, d_cnt, d_b, kMaxSeg);
+    int32_t cnt = 0;
+    RX(hipMemcpyAsync(&cnt, d_cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s), "class bounds");
+    RX(hipStreamSynchronize(s), "class bounds");
+    if (cnt + 2 > kMaxSeg) return fail("too many degree classes", hipErrorInvalidValue);
+    std::vector<int64_t> b((size_t)cnt);
+    if (cnt) RX(hipMemcpy(b.data(), d_b, sizeof(int64_t) * (size_t)cnt, hipMemcpyDeviceToHost), "class bounds");
+    std::sort(b.begin(), b.end());
+    b.insert(b.begin(), 0);
+    b.push_back(n);
+    RX(hipMalloc(&seg_lo, sizeof(int64_t) * (size_t)kMaxSeg), "segments");
+    RX(hipMemcpy(seg_lo, b.data(), sizeof(int64_t) * b.size(), hipMemcpyHostToDevice), "segments");
+    *nseg_out = (int32_t)b.size() - 1;
+  }
+  *seg_lo_out = seg_lo;
   *off_new_out = off_new;
   *idx_new_out = idx_new;
   *new2old_out = new2old;

@@ -39,14 +39,13 @@ def _run(dobfs, dg, root, **kw):
 
 
 def degree_class(d):
-    """Two classes per power of two: 2 * bit length + the bit below the
-    leading one; degree 0 is class 0."""
+    """One class per power of two: the bit length of the degree; degree 0
+    is class 0."""
     d = np.asarray(d, dtype=np.int64)
     bl = np.zeros_like(d)
     nz = d > 0
     bl[nz] = np.floor(np.log2(d[nz])).astype(np.int64) + 1
-    below = np.where(bl >= 2, (d >> np.maximum(bl - 2, 0)) & 1, 0)
-    return np.where(nz, 2 * bl + below, 0)
+    return bl
 
 
 def degree_relabel(g):
@@ -251,3 +250,12 @@ def test_reindex_device_source_and_parent_optional(dobfs):
         assert p is None and np.array_equal(d.cpu().numpy(), exp)
     # the source arrays are left untouched
     assert np.array_equal(off.cpu().numpy(), g.offsets) and np.array_equal(idx.cpu().numpy(), g.indices)
+
+
+def test_cost_policy(dobfs):
+    g = gg.kronecker(14, seed=12)
+    roots = gg.sample_roots(g, 3, seed=4)
+    for kap in (50, 500, 5000):
+        _parity(dobfs, g, roots, params=dobfs.make_params("cost", kappa_x1000=kap), label=f"kron14/cost{kap}")
+        _parity(dobfs, g, roots, params=dobfs.make_params("cost", kappa_x1000=kap), label=f"kron14/cost{kap}/reindex",
+                reindex=True)
