@@ -11,6 +11,17 @@ undirected edges per second, harmonic mean over every (root, step) run,
 where a run's traversed edges are the undirected edges of the root's
 component (half the summed degree of the reached vertices).
 
+Other modes (--mode), each printing one JSON line of its own:
+  batch  Kronecker scale 24: 64 roots in one batched pass against the same
+         64 roots run one at a time.
+  pack   2,000 Kronecker graphs of scales drawn uniformly from 10..18, one
+         root each, packed and traversed in one pass, against 2,000 separate
+         single-source runs.
+  serve  8 resident Kronecker graphs (scales 18, 20, 22, 24, 24, 25, 26, 26),
+         Poisson arrivals of (graph, root) queries at several rates, served
+         with continuous batching and, as the baseline, one plain run at a
+         time in arrival order; p50/p99 latency and completed queries/s.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -88,8 +99,253 @@ def cpu_baseline(scale: int, seed: int, nroots: int) -> dict:
                       f"harmonic mean; {total:.1f}s of CPU time"}
 
 
+def _timed(stream, fn):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    out = fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1), out
+
+
+def bench_batch(args) -> dict:
+    """64 roots in one batched pass vs the same roots one at a time."""
+    import torch
+    import graphgen as gg
+    import paper_1503_04359_amd as dobfs
+    scale, seed = args.scale if args.scale != 30 else 24, args.seed if args.seed != 2 else 4
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    g = gg.kronecker_device(scale, args.edgefactor, seed=seed)
+    roots = gg.sample_roots_device(g, 64, seed=seed + 1_000_000)
+    reindex = args.reindex == "on"
+    dg = dobfs.Graph.from_device_pointers(g.offsets_ptr, g.indices_ptr, g.n, g.m, borrow=not reindex,
+                                          reindex=reindex)
+    torch.cuda.synchronize()
+    log(f"[batch] kronecker scale {scale} resident in {time.time() - t0:.1f}s (n={g.n}, m={g.m})")
+    n = g.n
+    params = dobfs.make_params(args.policy)
+    out = torch.empty((64, n), dtype=torch.int32, device="cuda")
+    depth = torch.empty(n, dtype=torch.int32, device="cuda")
+    mc = []
+    for r in roots:  # traversed edges per root, and warm-up
+        _, _, st = dg.run(int(r), depth=depth, want_parent=False, params=params, stats=True, stream=stream)
+        mc.append(st.m_c)
+    dg.batch(roots, depth=out, params=params, stream=stream)
+    torch.cuda.synchronize()
+    bt, st_ = [], []
+    for _ in range(args.steps):
+        ms, _ = _timed(stream, lambda: dg.batch(roots, depth=out, params=params, stream=stream))
+        bt.append(ms)
+        ms_seq = 0.0
+        for r in roots:
+            t, _ = _timed(stream, lambda r=r: dg.run(int(r), depth=depth, want_parent=False, params=params,
+                                                         stream=stream))
+            ms_seq += t
+        st_.append(ms_seq)
+    # the batch must agree with the single runs
+    for b in (0, 31, 63):
+        dg.run(int(roots[b]), depth=depth, want_parent=False, params=params, stream=stream)
+        torch.cuda.synchronize()
+        if not torch.equal(depth, out[b]):
+            raise RuntimeError(f"batched depths of slot {b} differ from the single-source run")
+    batch_ms, seq_ms = min(bt), min(st_)
+    total_mc = float(sum(mc))
+    log(f"[batch] 64 roots: batched {batch_ms:.2f} ms, one at a time {seq_ms:.2f} ms "
+        f"({seq_ms / batch_ms:.2f}x)")
+    dg.free()
+    g.free()
+    return {"metric": f"batched GTEPS, 64 roots in one pass, kronecker scale {scale}",
+            "value": round(total_mc / (batch_ms * 1e-3) / 1e9, 3), "unit": "GTEPS", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": round(batch_ms, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": f"kronecker scale {scale} edgefactor {args.edgefactor} seed {seed}, 64 roots "
+                                   f"(seed {seed + 1_000_000}), batched vs single-source, degree relabel "
+                                   f"{args.reindex}, policy {args.policy}", "n": n, "m": g.m},
+            "sequential": {"ms": round(seq_ms, 3), "value": round(total_mc / (seq_ms * 1e-3) / 1e9, 3),
+                           "unit": "GTEPS"},
+            "speedup_vs_sequential": round(seq_ms / batch_ms, 3)}
+
+
+def bench_pack(args) -> dict:
+    """2,000 small graphs in one packed pass vs 2,000 single-source runs."""
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import paper_1503_04359_amd as dobfs
+    count = args.pack_graphs
+    rng = np.random.default_rng(4000)
+    scales = rng.integers(10, 19, size=count)
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    gs, roots = [], []
+    for i in range(count):
+        g = gg.kronecker_device(int(scales[i]), args.edgefactor, seed=4000 + i)
+        gs.append(g)
+        roots.append(int(gg.sample_roots_device(g, 1, seed=4000 + i + 1_000_000)[0]))
+    torch.cuda.synchronize()
+    n_tot = sum(g.n for g in gs)
+    m_tot = sum(g.m for g in gs)
+    log(f"[pack] built {count} graphs in {time.time() - t0:.1f}s: {n_tot} vertices, {m_tot} entries")
+    reindex = args.reindex == "on"
+    t0 = time.time()
+    pk = dobfs.Pack.upload(gs, reindex=reindex)
+    singles = [dobfs.Graph.from_device_pointers(g.offsets_ptr, g.indices_ptr, g.n, g.m, borrow=True)
+               for g in gs]
+    torch.cuda.synchronize()
+    log(f"[pack] pack and {count} single graphs resident in {time.time() - t0:.1f}s")
+    params = dobfs.make_params(args.policy)
+    out = torch.empty(pk.n, dtype=torch.int32, device="cuda")
+    depth = torch.empty(max(g.n for g in gs), dtype=torch.int32, device="cuda")
+    _, _, st = pk.run_pack(roots, depth=out, params=params, stats=True, stream=stream)
+    total_mc = float(st.m_c)
+    pt, stimes = [], []
+    for _ in range(args.steps):
+        ms, _ = _timed(stream, lambda: pk.run_pack(roots, depth=out, params=params, stream=stream))
+        pt.append(ms)
+
+        def seq():
+            for dg, r in zip(singles, roots):
+                dg.run(r, depth=depth, want_parent=False, params=params, stream=stream)
+        ms, _ = _timed(stream, seq)
+        stimes.append(ms)
+    # spot-check the pack against single runs
+    for i in (0, count // 2, count - 1):
+        singles[i].run(roots[i], depth=depth, want_parent=False, params=params, stream=stream)
+        torch.cuda.synchronize()
+        lo = int(pk.bases[i])
+        if not torch.equal(depth[:gs[i].n], out[lo:lo + gs[i].n]):
+            raise RuntimeError(f"packed depths of graph {i} differ from its single-source run")
+    pack_ms, seq_ms = min(pt), min(stimes)
+    log(f"[pack] {count} graphs: one pass {pack_ms:.2f} ms, one at a time {seq_ms:.2f} ms "
+        f"({seq_ms / pack_ms:.2f}x)")
+    for dg in singles:
+        dg.free()
+    pk.free()
+    for g in gs:
+        g.free()
+    return {"metric": f"packed graphs/s, {count} kronecker graphs of scale 10..18 in one pass",
+            "value": round(count / (pack_ms * 1e-3), 1), "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": round(pack_ms, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": f"{count} kronecker graphs, scales uniform over 10..18 (seed 4000), "
+                                   f"edgefactor {args.edgefactor}, graph seeds 4000+i, one root each, degree "
+                                   f"relabel {args.reindex}", "n": n_tot, "m": m_tot},
+            "gteps": round(total_mc / (pack_ms * 1e-3) / 1e9, 3),
+            "sequential": {"ms": round(seq_ms, 3), "value": round(count / (seq_ms * 1e-3), 1),
+                           "unit": "graphs/s"},
+            "speedup_vs_sequential": round(seq_ms / pack_ms, 3)}
+
+
+def _traversed_edges(dobfs, graphs, queries):
+    """Undirected edges each query's traversal covers: one run per graph
+    marks the component of its first root; other roots are run alone."""
+    import torch
+    import numpy as np
+    by_graph = {}
+    for q in queries:
+        by_graph.setdefault(q.gid, set()).add(q.root)
+    mc = {}
+    for gid, rs in by_graph.items():
+        g = graphs[gid]
+        rs = sorted(rs)
+        d, _, st = g.run(rs[0], want_parent=False, stats=True)
+        torch.cuda.synchronize()
+        comp = (d >= 0).cpu().numpy()
+        for r in rs:
+            if comp[r]:
+                mc[(gid, r)] = st.m_c
+            else:
+                _, _, s2 = g.run(r, want_parent=False, stats=True)
+                mc[(gid, r)] = s2.m_c
+    return mc
+
+
+def bench_serve(args) -> dict:
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import paper_1503_04359_amd as dobfs
+    from paper_1503_04359_amd import serve
+    scales = [18, 20, 22, 24, 24, 25, 26, 26]
+    reindex = args.reindex == "on"
+    t0 = time.time()
+    graphs, pools, dev = [], [], []
+    for j, sc in enumerate(scales):
+        g = gg.kronecker_device(sc, args.edgefactor, seed=5000 + j)
+        pools.append(gg.sample_roots_device(g, 256, seed=5000 + j + 1_000_000))
+        graphs.append(dobfs.Graph.from_device_pointers(g.offsets_ptr, g.indices_ptr, g.n, g.m,
+                                                       borrow=not reindex, reindex=reindex))
+        if reindex:
+            g.free()
+        else:
+            dev.append(g)
+    torch.cuda.synchronize()
+    log(f"[serve] {len(graphs)} graphs resident in {time.time() - t0:.1f}s "
+        f"({sum(g.n for g in graphs)} vertices)")
+    params = dobfs.make_params(args.policy, chunk_levels=args.serve_chunk)
+    ex = serve.GpuExecutor(graphs, params=params)
+    free, _ = torch.cuda.mem_get_info()
+    budget = max(0, free - (16 << 30))
+    srv = serve.Server(ex, memory_budget=budget)
+    # warm-up: one session and one plain run per graph
+    warm = [serve.Query(i, gid, int(pools[gid][0]), 0.0) for i, gid in enumerate(range(len(graphs)))]
+    srv.serve(warm, mode="batched", drain_s=30.0)
+    srv.serve(warm, mode="plain", drain_s=30.0)
+    rates = [float(x) for x in args.serve_rates.split(",")]
+    results = []
+    all_q = []
+    for rate in rates:
+        trace = serve.poisson_trace(rate, args.serve_duration, len(graphs), pools, seed=6000 + int(rate))
+        row = {"rate": rate, "offered": len(trace)}
+        for mode in ("batched", "plain"):
+            tr = [serve.Query(q.qid, q.gid, q.root, q.t_arrival) for q in trace]
+            torch.cuda.synchronize()
+            rep, _ = srv.serve(tr, mode=mode, drain_s=args.serve_drain)
+            all_q.extend(q for q in tr if q.t_done is not None)
+            row[mode] = rep.as_dict()
+            row[mode]["_queries"] = tr
+            log(f"[serve] rate {rate:g}/s {mode}: completed {rep.completed}/{rep.offered} "
+                f"({rep.unfinished} unfinished), {rep.qps:.0f} q/s, p50 {rep.p50_ms} ms, p99 {rep.p99_ms} ms")
+        results.append(row)
+    mc = _traversed_edges(dobfs, graphs, all_q)
+    for row in results:
+        for mode in ("batched", "plain"):
+            tr = row[mode].pop("_queries")
+            edges = sum(mc[(q.gid, q.root)] for q in tr if q.t_done is not None)
+            row[mode]["gteps"] = round(edges / row[mode]["makespan_s"] / 1e9, 3) if row[mode]["makespan_s"] else 0.0
+            row[mode].pop("per_graph", None)
+            for k in ("p50_ms", "p99_ms", "mean_ms", "qps", "makespan_s"):
+                if row[mode][k] is not None:
+                    row[mode][k] = round(row[mode][k], 3)
+    for g in graphs:
+        g.free()
+    for g in dev:
+        g.free()
+    top = results[-1]
+    return {"metric": "served queries/s + p99 vs plain (continuous batching)",
+            "value": top["batched"]["qps"], "unit": "queries/s", "n_gpus": 1, "steps": len(rates), "warmup": 1,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "int32", "data": "synthetic",
+            "config": {"workload": "8 resident kronecker graphs (scales 18,20,22,24,24,25,26,26, edgefactor "
+                                   f"{args.edgefactor}, seeds 5000+j), Poisson arrivals (seed 6000+rate) for "
+                                   f"{args.serve_duration:g} s per rate, uniform graph choice, roots from 256 per "
+                                   f"graph (seed 5000+j+10^6), degree relabel {args.reindex}, chunk "
+                                   f"{args.serve_chunk} levels, drain {args.serve_drain:g} s",
+                       "rates": rates},
+            "rates": results}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", choices=("single", "batch", "pack", "serve"), default="single")
+    ap.add_argument("--pack-graphs", type=int, default=2000)
+    ap.add_argument("--serve-rates", default="500,2000,8000")
+    ap.add_argument("--serve-duration", type=float, default=10.0)
+    ap.add_argument("--serve-drain", type=float, default=5.0)
+    ap.add_argument("--serve-chunk", type=int, default=4)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -122,6 +378,10 @@ def main() -> int:
     import paper_1503_04359_amd as dobfs
 
     torch.cuda.set_device(0)
+    if args.mode != "single":
+        fn = {"batch": bench_batch, "pack": bench_pack, "serve": bench_serve}[args.mode]
+        print(json.dumps(fn(args)), flush=True)
+        return 0
     stream = torch.cuda.current_stream()
     if args.copy_probe > 0:
         # elementwise copy kernel: reads and writes exactly `nbytes` each

@@ -167,7 +167,8 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
                        uint32_t flags, void* stream, dobfs_graph_t* out);
 
 /* Releases a graph and its workspaces after waiting for its runs to end.
-   NULL is accepted.  Errors: EDEVICE. */
+   NULL is accepted.  Errors: EBUSY (a session of the graph is open; nothing
+   is released), EDEVICE. */
 int dobfs_graph_free(dobfs_graph_t g);
 
 int dobfs_graph_info(dobfs_graph_t g, dobfs_graph_info_t* info);
@@ -186,6 +187,85 @@ int dobfs_graph_info(dobfs_graph_t g, dobfs_graph_info_t* info);
    Errors: EINVAL, ERANGE (root), ENOMEM (first-run workspace), EDEVICE. */
 int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, const dobfs_params* p,
               dobfs_stats* stats, void* stream);
+
+/* One traversal seeded from several roots at once (host int64[nroots],
+   caller IDs; duplicates allowed): depth = hop distance to the nearest root,
+   parent as for dobfs_run with every root its own parent.  Errors as for
+   dobfs_run, plus EINVAL when nroots < 1. */
+int dobfs_run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int32_t* depth, int32_t* parent,
+                    const dobfs_params* p, dobfs_stats* stats, void* stream);
+
+/* Many small graphs resident as one pack and traversed in one pass, one root
+   per graph.  Graph i keeps its own vertex IDs 0..n[i]-1; in the pack it
+   occupies IDs bases[i] .. bases[i+1]-1 (bases[0] = 0, bases[count] = total
+   vertices).  The graphs are disjoint, so one multi-root traversal gives
+   every graph its own single-source result.
+   dobfs_pack_upload: arrays of count pointers to each graph's CSR (host
+     memory, or device with DOBFS_SRC_DEVICE); flags as for upload except
+     DOBFS_BORROW.  The pack's vertex count must stay below 2^31.
+   dobfs_pack_bases: bases[0..count] into a host array of count+1.
+   dobfs_pack_run: roots: host int64[count], graph-local IDs.
+     depth: device int32[bases[count]], each graph's depths in its slice.
+     parent: device int32[bases[count]] or NULL, pack IDs (bases[i] + local).
+   Errors: EINVAL, ERANGE (a root outside its graph), ENOMEM, EDEVICE. */
+int dobfs_pack_upload(int32_t count, const int64_t* const* offsets, const int32_t* const* indices, const int64_t* n,
+                      const int64_t* m, uint32_t flags, void* stream, dobfs_graph_t* out);
+int dobfs_pack_bases(dobfs_graph_t pack, int64_t* bases);
+int dobfs_pack_run(dobfs_graph_t pack, const int64_t* roots, int32_t* depth, int32_t* parent, const dobfs_params* p,
+                   dobfs_stats* stats, void* stream);
+
+/* Up to 64 single-source traversals of one graph in one pass: slot b of a
+   64-bit mask per vertex follows root b (the same level-synchronous step of
+   Algorithm 1 applied to all slots at once; push or pull chosen per level
+   like dobfs_run).
+   roots:  host int64[k], caller IDs, duplicates allowed; 1 <= k <= 64.
+   depth:  device int32[k * n], root-major: depth[b*n + v] = hop distance of
+           v from roots[b], -1 if unreachable.  Parents are not produced.
+   stats:  NULL, or filled (totals over the k slots: reached, m_c).
+   Device memory: 32 bytes per vertex, plus 4*k per vertex of degree >= 1 on
+   relabelled graphs, allocated on the first batch and kept.
+   Errors: EINVAL (k, NULL), ERANGE (a root), ENOMEM, EDEVICE. */
+int dobfs_batch_submit(dobfs_graph_t g, const int64_t* roots, int32_t k, int32_t* depth, const dobfs_params* p,
+                       dobfs_stats* stats, void* stream);
+
+/* Continuous batching: a session keeps the 64 slots of the batched
+   traversal running and lets queries join and leave between level chunks.
+   A query joins at the session's current level with its root as its only
+   frontier vertex and counts its depths from there, so its result is the
+   same as a dobfs_run of that root alone, whatever else shares the session.
+   A slot is free again once its query's frontier is empty; its bit is
+   cleared from every vertex before the next query takes it.
+   The direction of each level is shared by all slots: it compares the
+   frontier (popcount-weighted) with the vertices the active slots could
+   still reach, using alpha and beta of the params.
+   A session holds one workspace of the graph (32 bytes per vertex) until
+   closed; several sessions on one graph are allowed.  All calls of one
+   session come from one thread and run on the session's stream.
+
+   dobfs_session_open: p NULL for defaults; stream as for dobfs_run.
+   dobfs_session_admit: queues a query; root in caller IDs; depth: device
+     int32[n] owned by the caller and not touched by it until the query is
+     reported done; it is set to -1 and then filled like dobfs_run's depth.
+     tag: the caller's name for the query, returned by dobfs_session_step.
+     Errors: ERANGE (root), EBUSY (64 queries admitted and not yet done).
+   dobfs_session_step: lets pending queries join, runs one chunk of
+     chunk_levels levels and waits for it; done_tags (host int64[cap])
+     receives the tags of the queries that ended (their depth arrays are
+     complete when the call returns), *n_done their number; queries beyond
+     cap are reported by the next calls.  Returns at once, with *n_done 0,
+     when nothing is admitted.
+   dobfs_session_counts: *active = queries holding a slot, *pending =
+     admitted but not yet joined, *levels = levels run so far.
+   dobfs_session_close: waits for the stream, forgets queries not reported
+     done and releases the workspace.  NULL is accepted.
+   Errors: EINVAL (NULL arguments), ERANGE, EBUSY, ENOMEM, EDEVICE. */
+typedef struct dobfs_session_s* dobfs_session_t;
+
+int dobfs_session_open(dobfs_graph_t g, const dobfs_params* p, void* stream, dobfs_session_t* out);
+int dobfs_session_admit(dobfs_session_t s, int64_t root, int32_t* depth, int64_t tag);
+int dobfs_session_step(dobfs_session_t s, int64_t* done_tags, int32_t cap, int32_t* n_done);
+int dobfs_session_counts(dobfs_session_t s, int32_t* active, int32_t* pending, int64_t* levels);
+int dobfs_session_close(dobfs_session_t s);
 
 /* Strings for a status; valid forever. */
 const char* dobfs_strerror(int status);

@@ -33,7 +33,9 @@ POLICIES = {"edge": POLICY_EDGE, "paper": POLICY_PAPER, "td": POLICY_FORCED_TD,
             "bu": POLICY_FORCED_BU, "random": POLICY_RANDOM, "cost": POLICY_COST}
 
 EXPORTED = ("dobfs_default_params", "dobfs_graph_upload", "dobfs_graph_free", "dobfs_graph_info",
-            "dobfs_run", "dobfs_strerror", "dobfs_last_error")
+            "dobfs_run", "dobfs_run_multi", "dobfs_batch_submit", "dobfs_pack_upload", "dobfs_pack_bases",
+            "dobfs_pack_run", "dobfs_session_open", "dobfs_session_admit", "dobfs_session_step",
+            "dobfs_session_counts", "dobfs_session_close", "dobfs_strerror", "dobfs_last_error")
 
 
 class DobfsError(RuntimeError):
@@ -84,6 +86,29 @@ _lib.dobfs_graph_info.restype = ctypes.c_int
 _lib.dobfs_graph_info.argtypes = [_vp, ctypes.POINTER(CGraphInfo)]
 _lib.dobfs_run.restype = ctypes.c_int
 _lib.dobfs_run.argtypes = [_vp, _i64, _vp, _vp, ctypes.POINTER(CParams), ctypes.POINTER(CStats), _vp]
+_lib.dobfs_batch_submit.restype = ctypes.c_int
+_lib.dobfs_batch_submit.argtypes = [_vp, _vp, ctypes.c_int32, _vp, ctypes.POINTER(CParams), ctypes.POINTER(CStats),
+                                    _vp]
+_lib.dobfs_run_multi.restype = ctypes.c_int
+_lib.dobfs_run_multi.argtypes = [_vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.POINTER(CParams), ctypes.POINTER(CStats),
+                                 _vp]
+_lib.dobfs_pack_upload.restype = ctypes.c_int
+_lib.dobfs_pack_upload.argtypes = [ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp, ctypes.POINTER(_vp)]
+_lib.dobfs_pack_bases.restype = ctypes.c_int
+_lib.dobfs_pack_bases.argtypes = [_vp, _vp]
+_lib.dobfs_pack_run.restype = ctypes.c_int
+_lib.dobfs_pack_run.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(CParams), ctypes.POINTER(CStats), _vp]
+_lib.dobfs_session_open.restype = ctypes.c_int
+_lib.dobfs_session_open.argtypes = [_vp, ctypes.POINTER(CParams), _vp, ctypes.POINTER(_vp)]
+_lib.dobfs_session_admit.restype = ctypes.c_int
+_lib.dobfs_session_admit.argtypes = [_vp, _i64, _vp, _i64]
+_lib.dobfs_session_step.restype = ctypes.c_int
+_lib.dobfs_session_step.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+_lib.dobfs_session_counts.restype = ctypes.c_int
+_lib.dobfs_session_counts.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(_i64)]
+_lib.dobfs_session_close.restype = ctypes.c_int
+_lib.dobfs_session_close.argtypes = [_vp]
 _lib.dobfs_strerror.restype = ctypes.c_char_p
 _lib.dobfs_strerror.argtypes = [ctypes.c_int]
 _lib.dobfs_last_error.restype = ctypes.c_char_p
@@ -123,6 +148,23 @@ class Stats:
 
     def dirs(self) -> list[int]:
         return [r["dir"] for r in self.log]
+
+
+def _make_stats(stats: bool, log_cap: int = 4096):
+    if not stats:
+        return None, None
+    log = (LevelRec * log_cap)()
+    cs = CStats()
+    cs.log = ctypes.cast(log, ctypes.POINTER(LevelRec))
+    cs.log_cap = log_cap
+    return cs, log
+
+
+def _read_stats(cs, log):
+    if cs is None:
+        return None
+    recs = [{f: getattr(log[i], f) for f, _ in LevelRec._fields_} for i in range(cs.log_len)]
+    return Stats(cs.levels, cs.reached, cs.m_c, cs.checked, recs, cs.level_launches, cs.level_kernel_ms)
 
 
 def _stream_ptr(stream):
@@ -221,6 +263,55 @@ class Graph:
                               cs.level_kernel_ms)
         return depth, parent, out_stats
 
+    def run_multi(self, roots, depth=None, parent=None, params: CParams | None = None, stats: bool = False,
+                  stream=None, want_parent: bool = True):
+        """One traversal from several roots: depth = distance to the nearest
+        root.  Returns (depth, parent, Stats|None)."""
+        import torch
+        r = np.ascontiguousarray(np.asarray(roots, dtype=np.int64).ravel())
+        if depth is None:
+            depth = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        if parent is None and want_parent:
+            parent = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        cs, log = _make_stats(stats)
+        _check(_lib.dobfs_run_multi(self._h, r.ctypes.data, int(r.shape[0]), _ptr(depth),
+                                    _ptr(parent) if parent is not None else None,
+                                    ctypes.byref(params) if params is not None else None,
+                                    ctypes.byref(cs) if cs is not None else None, _stream_ptr(stream)),
+               "dobfs_run_multi")
+        return depth, parent, _read_stats(cs, log)
+
+    def batch(self, roots, depth=None, params: CParams | None = None, stats: bool = False, stream=None,
+              log_cap: int = 4096):
+        """Up to 64 traversals in one pass.  Returns (depth int32[k, n]
+        CUDA tensor, root-major; Stats|None with totals over the slots)."""
+        import torch
+        r = np.ascontiguousarray(np.asarray(roots, dtype=np.int64).ravel())
+        k = int(r.shape[0])
+        if depth is None:
+            depth = torch.empty((k, self.n), dtype=torch.int32, device="cuda")
+        if depth.dtype != torch.int32 or depth.numel() < k * self.n or not depth.is_cuda or not depth.is_contiguous():
+            raise ValueError("depth must be a contiguous int32 CUDA tensor of k*n elements")
+        cs = log = None
+        if stats:
+            log = (LevelRec * log_cap)()
+            cs = CStats()
+            cs.log = ctypes.cast(log, ctypes.POINTER(LevelRec))
+            cs.log_cap = log_cap
+        _check(_lib.dobfs_batch_submit(self._h, r.ctypes.data, k, _ptr(depth),
+                                       ctypes.byref(params) if params is not None else None,
+                                       ctypes.byref(cs) if cs is not None else None, _stream_ptr(stream)),
+               "dobfs_batch_submit")
+        out = None
+        if stats:
+            recs = [{f: getattr(log[i], f) for f, _ in LevelRec._fields_} for i in range(cs.log_len)]
+            out = Stats(cs.levels, cs.reached, cs.m_c, cs.checked, recs, cs.level_launches, cs.level_kernel_ms)
+        return depth, out
+
+    def session(self, params: CParams | None = None, stream=None) -> "Session":
+        """A continuous-batching session over this graph."""
+        return Session(self, params, stream)
+
     def free(self) -> None:
         if self._h:
             _check(_lib.dobfs_graph_free(self._h), "dobfs_graph_free")
@@ -237,3 +328,116 @@ class Graph:
 
     def __exit__(self, *exc):
         self.free()
+
+
+class Session:
+    """Continuous batching over one graph: queries join the running 64-slot
+    traversal between level chunks and leave when their frontier empties."""
+
+    SLOTS = 64
+
+    def __init__(self, graph: Graph, params: CParams | None = None, stream=None):
+        self.graph = graph
+        self._h = ctypes.c_void_p()
+        self._done = np.zeros(self.SLOTS, dtype=np.int64)
+        self._nd = ctypes.c_int32()
+        self._outs: dict[int, object] = {}
+        _check(_lib.dobfs_session_open(graph._h, ctypes.byref(params) if params is not None else None,
+                                       _stream_ptr(stream), ctypes.byref(self._h)), "dobfs_session_open")
+
+    def admit(self, root: int, tag: int, depth=None):
+        """Queue a query; returns its depth tensor (complete once `tag` is
+        reported by step()).  Raises DobfsError(EBUSY) when 64 are in flight."""
+        import torch
+        if depth is None:
+            depth = torch.empty(self.graph.n, dtype=torch.int32, device="cuda")
+        if depth.dtype != torch.int32 or depth.numel() < self.graph.n or not depth.is_cuda:
+            raise ValueError("depth must be an int32 CUDA tensor of n elements")
+        _check(_lib.dobfs_session_admit(self._h, int(root), _ptr(depth), int(tag)), "dobfs_session_admit")
+        self._outs[int(tag)] = depth
+        return depth
+
+    def step(self) -> list[tuple[int, object]]:
+        """One level chunk; returns [(tag, depth tensor)] of the queries that
+        ended."""
+        _check(_lib.dobfs_session_step(self._h, self._done.ctypes.data, self.SLOTS, ctypes.byref(self._nd)),
+               "dobfs_session_step")
+        return [(int(t), self._outs.pop(int(t))) for t in self._done[:self._nd.value]]
+
+    def counts(self) -> tuple[int, int, int]:
+        a, p, lv = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(_lib.dobfs_session_counts(self._h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(lv)),
+               "dobfs_session_counts")
+        return a.value, p.value, lv.value
+
+    def close(self) -> None:
+        if self._h:
+            _check(_lib.dobfs_session_close(self._h), "dobfs_session_close")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Pack(Graph):
+    """Many small graphs resident as one pack, traversed in one pass with
+    one root per graph."""
+
+    def __init__(self, handle, n: int, m: int, bases: np.ndarray):
+        super().__init__(handle, n, m)
+        self.bases = bases
+
+    @classmethod
+    def upload(cls, graphs, *, reindex: bool = False, check_symmetry: bool = False, stream=None) -> "Pack":
+        """graphs: sequence of (offsets, indices) as host numpy arrays, or of
+        objects with offsets_ptr/indices_ptr/n/m (device CSRs)."""
+        count = len(graphs)
+        offp = (ctypes.c_void_p * count)()
+        idxp = (ctypes.c_void_p * count)()
+        ns = np.zeros(count, dtype=np.int64)
+        ms = np.zeros(count, dtype=np.int64)
+        keep = []
+        device = hasattr(graphs[0], "offsets_ptr")
+        for i, gr in enumerate(graphs):
+            if device:
+                offp[i], idxp[i], ns[i], ms[i] = gr.offsets_ptr, gr.indices_ptr, gr.n, gr.m
+            else:
+                off = np.ascontiguousarray(gr[0], dtype=np.int64)
+                idx = np.ascontiguousarray(gr[1], dtype=np.int32)
+                keep.append((off, idx))
+                offp[i], idxp[i] = off.ctypes.data, (idx.ctypes.data if idx.shape[0] else None)
+                ns[i], ms[i] = off.shape[0] - 1, idx.shape[0]
+        flags = VALIDATE | (SRC_DEVICE if device else 0) | (VALIDATE_SYMMETRY if check_symmetry else 0)
+        flags |= REINDEX_DEGREE if reindex else 0
+        h = ctypes.c_void_p()
+        _check(_lib.dobfs_pack_upload(count, offp, idxp, ns.ctypes.data, ms.ctypes.data, flags, _stream_ptr(stream),
+                                      ctypes.byref(h)), "dobfs_pack_upload")
+        bases = np.zeros(count + 1, dtype=np.int64)
+        _check(_lib.dobfs_pack_bases(h, bases.ctypes.data), "dobfs_pack_bases")
+        return cls(h, int(bases[-1]), int(ms.sum()), bases)
+
+    def run_pack(self, roots, depth=None, parent=None, params: CParams | None = None, stats: bool = False,
+                 stream=None, want_parent: bool = False):
+        """roots: one graph-local root per graph.  Returns (depth, parent,
+        Stats|None) over the pack's IDs; parents are pack IDs."""
+        import torch
+        r = np.ascontiguousarray(np.asarray(roots, dtype=np.int64).ravel())
+        if depth is None:
+            depth = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        if parent is None and want_parent:
+            parent = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        cs, log = _make_stats(stats)
+        _check(_lib.dobfs_pack_run(self._h, r.ctypes.data, _ptr(depth), _ptr(parent) if parent is not None else None,
+                                   ctypes.byref(params) if params is not None else None,
+                                   ctypes.byref(cs) if cs is not None else None, _stream_ptr(stream)),
+               "dobfs_pack_run")
+        return depth, parent, _read_stats(cs, log)

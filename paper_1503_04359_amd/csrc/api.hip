@@ -4,6 +4,7 @@
  */
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -59,9 +60,19 @@ struct Workspace {
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t idle = nullptr;     /* recorded after the last kernel of a run */
   std::vector<hipEvent_t> tev;   /* level-kernel timing events, 2 per launch */
+  /* batched traversals, allocated on first use */
+  uint64_t* ms_visit = nullptr;
+  uint64_t* ms_cur0 = nullptr;
+  uint64_t* ms_cur1 = nullptr;
+  uint64_t* ms_nxt = nullptr;
+  int32_t* ms_internal = nullptr;
+  int64_t ms_internal_cap = 0;
+  int32_t* roots_dev = nullptr;   /* multi-root runs */
+  int64_t roots_cap = 0;
   bool busy = false;
 
   void release() {
+    dfree(ms_visit); dfree(ms_cur0); dfree(ms_cur1); dfree(ms_nxt); dfree(ms_internal); dfree(roots_dev);
     dfree(vis); dfree(fr0); dfree(fr1); dfree(q0);
     dfree(huge_u); dfree(huge_base); dfree(parent_scratch); dfree(packed); dfree(ctl); dfree(log);
     if (done_host) (void)hipHostFree(done_host);
@@ -92,6 +103,8 @@ struct dobfs_graph_s {
   int32_t* old2new = nullptr;
   int64_t* seg_lo = nullptr;
   int32_t nseg = 0;
+  std::vector<int64_t> pack_base;  /* packs: first union ID of each graph, then n */
+  int open_sessions = 0;
   int device = 0;
   int grid = 0;
   std::mutex mu;
@@ -114,6 +127,29 @@ struct dobfs_graph_s {
     g.words_active = words_active;
     return g;
   }
+};
+
+struct dobfs_session_s {
+  dobfs_graph_s* g = nullptr;
+  Workspace* w = nullptr;
+  hipStream_t stream = nullptr;
+  dobfs_params prm;
+  KParams kp;
+  int32_t** slot_out = nullptr;  /* device tables read by the kernels */
+  int32_t* slot_start = nullptr;
+  dobfs::Ctl* host_ctl = nullptr;  /* pinned copy of the control block */
+  hipEvent_t ev = nullptr;
+  uint64_t active = 0;   /* slots whose query runs */
+  uint64_t dirty = 0;    /* slots whose bits still mark an ended query */
+  int64_t tag[64] = {};
+  struct Pending {
+    int32_t root;
+    int32_t* depth;
+    int64_t tag;
+  };
+  std::vector<Pending> pending;
+  std::vector<int64_t> done;  /* ended, not yet reported */
+  int64_t levels = 0;
 };
 
 namespace {
@@ -209,6 +245,84 @@ int first_direction(const dobfs_params& p) {
     return (int)(z & 1ull);
   }
   return kDirTD;
+}
+
+/* Host side of the level loop: chunks of K levels, each enqueued by
+   `level(i)`, with one chunk always queued ahead of the one whose done flag
+   the host waits for.  Returns the number of level slots enqueued. */
+template <class LevelFn>
+int level_loop(Workspace* w, const Ctl* ctl_dev, int K, int64_t max_levels, hipStream_t s, LevelFn level,
+               int64_t* enqueued) {
+  int64_t launches = 0;
+  auto chunk = [&](int slot) -> int {
+    for (int i = 0; i < K; ++i) {
+      const int st = level(launches);
+      if (st != DOBFS_OK) return st;
+      ++launches;
+    }
+    DOBFS_HIP(hipMemcpyAsync(&w->done_host[slot], &ctl_dev->done, sizeof(int32_t), hipMemcpyDeviceToHost, s),
+              "done flag copy");
+    DOBFS_HIP(hipEventRecord(w->ev[slot], s), "event record");
+    return DOBFS_OK;
+  };
+  int st = chunk(0);
+  if (st != DOBFS_OK) return st;
+  const int64_t max_chunks = max_levels / K + 3;
+  for (int64_t c = 0;; ++c) {
+    if (c + 1 >= max_chunks) return fail(DOBFS_EDEVICE, "level loop did not terminate");
+    if ((st = chunk((int)((c + 1) & 1))) != DOBFS_OK) return st;
+    DOBFS_HIP(hipEventSynchronize(w->ev[c & 1]), "level chunk");
+    if (w->done_host[c & 1]) break;
+  }
+  *enqueued = launches;
+  return DOBFS_OK;
+}
+
+int ensure_ms_buffers(dobfs_graph_s* g, Workspace* w, int32_t k) {
+  hipError_t e = hipSuccess;
+  if (!w->ms_visit) {
+    if ((e = dalloc(&w->ms_visit, g->n)) != hipSuccess || (e = dalloc(&w->ms_cur0, g->n)) != hipSuccess ||
+        (e = dalloc(&w->ms_cur1, g->n)) != hipSuccess || (e = dalloc(&w->ms_nxt, g->n)) != hipSuccess) {
+      dfree(w->ms_visit); dfree(w->ms_cur0); dfree(w->ms_cur1); dfree(w->ms_nxt);
+      w->ms_visit = w->ms_cur0 = w->ms_cur1 = w->ms_nxt = nullptr;
+      return fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "batch workspace", e);
+    }
+  }
+  if (g->new2old) {
+    const int64_t need = g->n_nonisolated * (int64_t)k;
+    if (need > w->ms_internal_cap) {
+      dfree(w->ms_internal);
+      w->ms_internal = nullptr;
+      w->ms_internal_cap = 0;
+      if ((e = dalloc(&w->ms_internal, need)) != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "batch labels", e);
+      w->ms_internal_cap = need;
+    }
+  }
+  return DOBFS_OK;
+}
+
+int fill_stats(Workspace* w, hipStream_t s, dobfs_stats* stats, int64_t launches, const std::vector<float>& kms) {
+  Ctl ctl;
+  DOBFS_HIP(hipMemcpyAsync(&ctl, w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "stats copy");
+  DOBFS_HIP(hipStreamSynchronize(s), "stats sync");
+  stats->level_launches = (int32_t)launches;
+  stats->level_kernel_ms = 0.0;
+  for (float x : kms) stats->level_kernel_ms += x;
+  stats->levels = ctl.levels;
+  stats->log_len = ctl.log_len < w->log_cap ? ctl.log_len : w->log_cap;
+  stats->reached = ctl.reached;
+  stats->m_c = ctl.reached_deg / 2;
+  stats->checked = ctl.checked_total;
+  stats->t_begin = ctl.t_begin;
+  if (stats->log && stats->log_cap > 0) {
+    const int32_t k = stats->log_len < stats->log_cap ? stats->log_len : stats->log_cap;
+    if (k > 0)
+      DOBFS_HIP(hipMemcpy(stats->log, w->log, sizeof(dobfs_level_rec) * (size_t)k, hipMemcpyDeviceToHost),
+                "log copy");
+    for (int32_t i = 0; i < k; ++i) stats->log[i].kernel_ms = i < (int32_t)kms.size() ? kms[(size_t)i] : 0.f;
+  }
+  return DOBFS_OK;
 }
 
 }  // namespace
@@ -375,6 +489,7 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
 
 int dobfs_graph_free(dobfs_graph_t g) {
   if (!g) return DOBFS_OK;
+  if (g->open_sessions > 0) return fail(DOBFS_EBUSY, "a session of this graph is still open");
   for (Workspace* w : g->pool) {
     if (w->idle) (void)hipEventSynchronize(w->idle);
     w->release();
@@ -406,11 +521,19 @@ int dobfs_graph_info(dobfs_graph_t g, dobfs_graph_info_t* info) {
   return DOBFS_OK;
 }
 
-int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, const dobfs_params* p,
-              dobfs_stats* stats, void* stream) {
+/* One traversal seeded from nroots roots (host caller IDs in roots), or
+   from root when roots is NULL. */
+static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int64_t root, int32_t* depth,
+                     int32_t* parent, const dobfs_params* p, dobfs_stats* stats, void* stream) {
   g_last_error.clear();
   if (!g || !depth) return fail(DOBFS_EINVAL, "graph or depth is NULL");
-  if (root < 0 || root >= g->n) return fail(DOBFS_ERANGE, "root outside [0, n)");
+  if (roots) {
+    if (nroots < 1) return fail(DOBFS_EINVAL, "no roots");
+    for (int32_t i = 0; i < nroots; ++i)
+      if (roots[i] < 0 || roots[i] >= g->n) return fail(DOBFS_ERANGE, "root outside [0, n)");
+  } else if (root < 0 || root >= g->n) {
+    return fail(DOBFS_ERANGE, "root outside [0, n)");
+  }
   dobfs_params prm;
   if (p) prm = *p; else dobfs_default_params(&prm);
   int st = check_params(prm);
@@ -423,7 +546,6 @@ int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, co
     Workspace* w;
     ~Guard() { release_workspace(g, w); }
   } guard{g, w};
-
   if (!parent && !g->new2old) {
     if (!w->parent_scratch) {
       hipError_t e = dalloc(&w->parent_scratch, g->n);
@@ -448,73 +570,354 @@ int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, co
   wv.pad = 0;
   const KParams kp = to_kparams(prm);
 
-  DOBFS_HIP(launch_init(gv, wv, root, first_direction(prm), g->grid, s), "init launch");
-  const int K = prm.chunk_levels;
-  const bool timed = (prm.flags & DOBFS_RUN_TIME_KERNELS) != 0;
-  int64_t launches = 0;
-  auto enqueue_chunk = [&](int slot) -> int {
-    for (int i = 0; i < K; ++i) {
-      if (timed) {
-        while ((int64_t)w->tev.size() < 2 * (launches + 1)) {
-          hipEvent_t ev;
-          DOBFS_HIP(hipEventCreate(&ev), "timing event");
-          w->tev.push_back(ev);
-        }
-        DOBFS_HIP(hipEventRecord(w->tev[2 * launches], s), "timing event");
-      }
-      DOBFS_HIP(launch_level(gv, wv, kp, g->grid, s), "level launch");
-      if (timed) DOBFS_HIP(hipEventRecord(w->tev[2 * launches + 1], s), "timing event");
-      ++launches;
-      DOBFS_HIP(launch_aux(gv, wv, kp, g->grid, s), "aux launch");
+  const int32_t* roots_dev = nullptr;
+  if (roots) {
+    if (w->roots_cap < nroots) {
+      dfree(w->roots_dev);
+      w->roots_dev = nullptr;
+      w->roots_cap = 0;
+      hipError_t e = dalloc(&w->roots_dev, nroots);
+      if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "roots", e);
+      w->roots_cap = nroots;
     }
-    DOBFS_HIP(hipMemcpyAsync(&w->done_host[slot], &w->ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, s),
-              "done flag copy");
-    DOBFS_HIP(hipEventRecord(w->ev[slot], s), "event record");
+    std::vector<int32_t> r32(roots, roots + nroots);
+    DOBFS_HIP(hipMemcpyAsync(w->roots_dev, r32.data(), sizeof(int32_t) * (size_t)nroots, hipMemcpyHostToDevice, s),
+              "roots copy");
+    DOBFS_HIP(hipStreamSynchronize(s), "roots copy");
+    roots_dev = w->roots_dev;
+  }
+  DOBFS_HIP(launch_init(gv, wv, roots_dev, roots ? nroots : 1, root, first_direction(prm), g->grid, s),
+            "init launch");
+  const bool timed = (prm.flags & DOBFS_RUN_TIME_KERNELS) != 0;
+  auto level = [&](int64_t i) -> int {
+    if (timed) {
+      while ((int64_t)w->tev.size() < 2 * (i + 1)) {
+        hipEvent_t ev;
+        DOBFS_HIP(hipEventCreate(&ev), "timing event");
+        w->tev.push_back(ev);
+      }
+      DOBFS_HIP(hipEventRecord(w->tev[2 * i], s), "timing event");
+    }
+    DOBFS_HIP(launch_level(gv, wv, kp, g->grid, s), "level launch");
+    if (timed) DOBFS_HIP(hipEventRecord(w->tev[2 * i + 1], s), "timing event");
+    DOBFS_HIP(launch_aux(gv, wv, kp, g->grid, s), "aux launch");
     return DOBFS_OK;
   };
-  /* One chunk is always queued ahead of the one being waited for, so the
-     device never idles on the host's check. */
-  if ((st = enqueue_chunk(0)) != DOBFS_OK) return st;
-  const int64_t max_chunks = (g->n + 1) / K + 3;
-  for (int64_t c = 0;; ++c) {
-    if (c + 1 >= max_chunks) return fail(DOBFS_EDEVICE, "level loop did not terminate");
-    if ((st = enqueue_chunk((int)((c + 1) & 1))) != DOBFS_OK) return st;
-    DOBFS_HIP(hipEventSynchronize(w->ev[c & 1]), "level chunk");
-    if (w->done_host[c & 1]) break;
+  int64_t launches = 0;
+  if ((st = level_loop(w, w->ctl, prm.chunk_levels, g->n + 1, s, level, &launches)) != DOBFS_OK) return st;
+  if (g->new2old) {
+    DOBFS_HIP(launch_finalize(gv, wv, roots ? -1 : root, g->grid, s), "finalize launch");
+    if (roots) DOBFS_HIP(launch_fix_roots(wv, roots_dev, nroots, s), "root labels launch");
   }
-  if (g->new2old) DOBFS_HIP(launch_finalize(gv, wv, root, g->grid, s), "finalize launch");
   DOBFS_HIP(hipEventRecord(w->idle, s), "idle event");
-  if (stats || timed) {
-    Ctl ctl;
-    DOBFS_HIP(hipMemcpyAsync(&ctl, w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "stats copy");
-    DOBFS_HIP(hipStreamSynchronize(s), "stats sync");
-    if (!stats) return DOBFS_OK;
-    stats->level_launches = (int32_t)launches;
-    stats->level_kernel_ms = 0.0;
-    std::vector<float> kms;
-    if (timed) {
-      kms.resize((size_t)launches);
-      for (int64_t i = 0; i < launches; ++i) {
-        float ms = 0.f;
-        DOBFS_HIP(hipEventElapsedTime(&ms, w->tev[2 * i], w->tev[2 * i + 1]), "timing");
-        kms[(size_t)i] = ms;
-        stats->level_kernel_ms += ms;
-      }
-    }
-    stats->levels = ctl.levels;
-    stats->log_len = ctl.log_len < w->log_cap ? ctl.log_len : w->log_cap;
-    stats->reached = ctl.reached;
-    stats->m_c = ctl.reached_deg / 2;
-    stats->checked = ctl.checked_total;
-    stats->t_begin = ctl.t_begin;
-    if (stats->log && stats->log_cap > 0) {
-      const int32_t k = stats->log_len < stats->log_cap ? stats->log_len : stats->log_cap;
-      if (k > 0)
-        DOBFS_HIP(hipMemcpy(stats->log, w->log, sizeof(dobfs_level_rec) * (size_t)k, hipMemcpyDeviceToHost),
-                  "log copy");
-      for (int32_t i = 0; i < k; ++i) stats->log[i].kernel_ms = i < (int32_t)kms.size() ? kms[(size_t)i] : 0.f;
-    }
+  if (!stats) return DOBFS_OK;
+  std::vector<float> kms;
+  if (timed) {
+    kms.resize((size_t)launches);
+    for (int64_t i = 0; i < launches; ++i)
+      DOBFS_HIP(hipEventElapsedTime(&kms[(size_t)i], w->tev[2 * i], w->tev[2 * i + 1]), "timing");
   }
+  return fill_stats(w, s, stats, launches, kms);
+}
+
+int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, const dobfs_params* p,
+              dobfs_stats* stats, void* stream) {
+  return run_multi(g, nullptr, 0, root, depth, parent, p, stats, stream);
+}
+
+int dobfs_run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int32_t* depth, int32_t* parent,
+                    const dobfs_params* p, dobfs_stats* stats, void* stream) {
+  if (!roots) return fail(DOBFS_EINVAL, "roots is NULL");
+  return run_multi(g, roots, nroots, -1, depth, parent, p, stats, stream);
+}
+
+int dobfs_batch_submit(dobfs_graph_t g, const int64_t* roots, int32_t k, int32_t* depth, const dobfs_params* p,
+                       dobfs_stats* stats, void* stream) {
+  g_last_error.clear();
+  if (!g || !roots || !depth) return fail(DOBFS_EINVAL, "graph, roots or depth is NULL");
+  if (k < 1 || k > 64) return fail(DOBFS_EINVAL, "k must be in [1, 64]");
+  MsRoots r;
+  std::memset(&r, 0, sizeof(r));
+  for (int32_t b = 0; b < k; ++b) {
+    if (roots[b] < 0 || roots[b] >= g->n) return fail(DOBFS_ERANGE, "root outside [0, n)");
+    r.r[b] = (int32_t)roots[b];
+  }
+  dobfs_params prm;
+  if (p) prm = *p; else dobfs_default_params(&prm);
+  int st = check_params(prm);
+  if (st != DOBFS_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Workspace* w = nullptr;
+  if ((st = acquire_workspace(g, &w)) != DOBFS_OK) return st;
+  struct Guard {
+    dobfs_graph_s* g;
+    Workspace* w;
+    ~Guard() { release_workspace(g, w); }
+  } guard{g, w};
+  if ((st = ensure_ms_buffers(g, w, k)) != DOBFS_OK) return st;
+  const GView gv = g->view();
+  MsView m;
+  m.visit = w->ms_visit;
+  m.cur0 = w->ms_cur0;
+  m.cur1 = w->ms_cur1;
+  m.nxt = w->ms_nxt;
+  m.out = depth;
+  m.internal = g->new2old ? w->ms_internal : nullptr;
+  m.k = k;
+  m.pad = 0;
+  m.full = k == 64 ? ~0ull : ((1ull << k) - 1ull);
+  m.ctl = w->ctl;
+  m.log = w->log;
+  m.log_cap = w->log_cap;
+  m.session = 0;
+  m.slot_out = nullptr;
+  m.slot_start = nullptr;
+  const KParams kp = to_kparams(prm);
+  DOBFS_HIP(launch_ms_init(gv, m, r, g->grid, s), "batch init launch");
+  auto level = [&](int64_t) -> int {
+    DOBFS_HIP(launch_ms_level(gv, m, kp, g->grid, s), "batch level launch");
+    return DOBFS_OK;
+  };
+  int64_t launches = 0;
+  if ((st = level_loop(w, w->ctl, prm.chunk_levels, g->n + 1, s, level, &launches)) != DOBFS_OK) return st;
+  if (g->new2old) DOBFS_HIP(launch_ms_finalize(gv, m, r, g->grid, s), "batch finalize launch");
+  DOBFS_HIP(hipEventRecord(w->idle, s), "idle event");
+  if (!stats) return DOBFS_OK;
+  return fill_stats(w, s, stats, launches, std::vector<float>());
+}
+
+int dobfs_pack_upload(int32_t count, const int64_t* const* offsets, const int32_t* const* indices, const int64_t* n,
+                      const int64_t* m, uint32_t flags, void* stream, dobfs_graph_t* out) {
+  g_last_error.clear();
+  if (!out) return fail(DOBFS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || !offsets || !indices || !n || !m) return fail(DOBFS_EINVAL, "empty pack or NULL arrays");
+  if (flags & ~(DOBFS_SRC_DEVICE | DOBFS_VALIDATE | DOBFS_VALIDATE_SYMMETRY | DOBFS_REINDEX_DEGREE))
+    return fail(DOBFS_EINVAL, "unknown flag");
+  std::vector<int64_t> nb((size_t)count + 1, 0), mb((size_t)count + 1, 0);
+  for (int32_t i = 0; i < count; ++i) {
+    if (!offsets[i] || (!indices[i] && m[i] > 0) || n[i] < 1 || m[i] < 0) return fail(DOBFS_EINVAL, "bad graph in pack");
+    nb[(size_t)i + 1] = nb[(size_t)i] + n[i];
+    mb[(size_t)i + 1] = mb[(size_t)i] + m[i];
+  }
+  const int64_t N = nb[(size_t)count], M = mb[(size_t)count];
+  if (N > 2147483647LL) return fail(DOBFS_EINVAL, "pack has more than 2^31-1 vertices");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int64_t* uoff = nullptr;
+  int32_t* uidx = nullptr;
+  hipError_t e;
+  if ((e = dalloc(&uoff, N + 1)) != hipSuccess || (e = dalloc(&uidx, M)) != hipSuccess) {
+    dfree(uoff);
+    dfree(uidx);
+    return fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "pack allocation", e);
+  }
+  const bool dev = (flags & DOBFS_SRC_DEVICE) != 0;
+  int st = DOBFS_OK;
+  for (int32_t i = 0; i < count && st == DOBFS_OK; ++i) {
+    e = launch_pack_copy(offsets[i], indices[i], n[i], m[i], nb[(size_t)i], mb[(size_t)i], dev, uoff, uidx, s);
+    if (e != hipSuccess) st = fail(DOBFS_EDEVICE, "pack copy", e);
+  }
+  if (st == DOBFS_OK && (e = hipStreamSynchronize(s)) != hipSuccess) st = fail(DOBFS_EDEVICE, "pack copy", e);
+  if (st != DOBFS_OK) {
+    dfree(uoff);
+    dfree(uidx);
+    return st;
+  }
+  const bool reindex = (flags & DOBFS_REINDEX_DEGREE) != 0;
+  dobfs_graph_t g = nullptr;
+  st = dobfs_graph_upload(uoff, uidx, N, M, (flags & ~DOBFS_SRC_DEVICE) | DOBFS_SRC_DEVICE | (reindex ? 0u : DOBFS_BORROW),
+                          stream, &g);
+  if (st != DOBFS_OK || reindex) {
+    dfree(uoff);
+    dfree(uidx);
+  }
+  if (st != DOBFS_OK) return st;
+  if (!reindex) g->owns_csr = true;  /* the union arrays now belong to the graph */
+  g->pack_base = nb;
+  *out = g;
+  return DOBFS_OK;
+}
+
+int dobfs_pack_bases(dobfs_graph_t pack, int64_t* bases) {
+  if (!pack || !bases) return fail(DOBFS_EINVAL, "NULL argument");
+  if (pack->pack_base.empty()) return fail(DOBFS_EINVAL, "not a pack");
+  for (size_t i = 0; i < pack->pack_base.size(); ++i) bases[i] = pack->pack_base[i];
+  return DOBFS_OK;
+}
+
+int dobfs_pack_run(dobfs_graph_t pack, const int64_t* roots, int32_t* depth, int32_t* parent, const dobfs_params* p,
+                   dobfs_stats* stats, void* stream) {
+  g_last_error.clear();
+  if (!pack || !roots || !depth) return fail(DOBFS_EINVAL, "pack, roots or depth is NULL");
+  if (pack->pack_base.empty()) return fail(DOBFS_EINVAL, "not a pack");
+  const int32_t count = (int32_t)pack->pack_base.size() - 1;
+  std::vector<int64_t> global((size_t)count);
+  for (int32_t i = 0; i < count; ++i) {
+    const int64_t lo = pack->pack_base[(size_t)i], hi = pack->pack_base[(size_t)i + 1];
+    if (roots[i] < 0 || lo + roots[i] >= hi) return fail(DOBFS_ERANGE, "root outside its graph");
+    global[(size_t)i] = lo + roots[i];
+  }
+  return run_multi(pack, global.data(), count, -1, depth, parent, p, stats, stream);
+}
+
+static int session_view(dobfs_session_s* ss, MsView* m) {
+  Workspace* w = ss->w;
+  m->visit = w->ms_visit;
+  m->cur0 = w->ms_cur0;
+  m->cur1 = w->ms_cur1;
+  m->nxt = w->ms_nxt;
+  m->out = nullptr;
+  m->internal = nullptr;
+  m->k = 64;
+  m->pad = 0;
+  m->full = ss->active;
+  m->ctl = w->ctl;
+  m->log = w->log;
+  m->log_cap = 0;
+  m->session = 1;
+  m->slot_out = ss->slot_out;
+  m->slot_start = ss->slot_start;
+  return DOBFS_OK;
+}
+
+int dobfs_session_open(dobfs_graph_t g, const dobfs_params* p, void* stream, dobfs_session_t* out) {
+  g_last_error.clear();
+  if (!g || !out) return fail(DOBFS_EINVAL, "graph or out is NULL");
+  *out = nullptr;
+  dobfs_params prm;
+  if (p) prm = *p; else dobfs_default_params(&prm);
+  int st = check_params(prm);
+  if (st != DOBFS_OK) return st;
+  dobfs_session_s* ss = new (std::nothrow) dobfs_session_s();
+  if (!ss) return fail(DOBFS_ENOMEM, "session");
+  ss->g = g;
+  ss->stream = reinterpret_cast<hipStream_t>(stream);
+  ss->prm = prm;
+  ss->kp = to_kparams(prm);
+  auto undo = [&](int status) {
+    dfree(ss->slot_out);
+    dfree(ss->slot_start);
+    if (ss->host_ctl) (void)hipHostFree(ss->host_ctl);
+    if (ss->ev) (void)hipEventDestroy(ss->ev);
+    if (ss->w) release_workspace(g, ss->w);
+    delete ss;
+    return status;
+  };
+  if ((st = acquire_workspace(g, &ss->w)) != DOBFS_OK) {
+    ss->w = nullptr;
+    return undo(st);
+  }
+  if ((st = ensure_ms_buffers(g, ss->w, 0)) != DOBFS_OK) return undo(st);
+  hipError_t e;
+  if ((e = dalloc(&ss->slot_out, 64)) != hipSuccess || (e = dalloc(&ss->slot_start, 64)) != hipSuccess)
+    return undo(fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "session tables", e));
+  if ((e = hipHostMalloc(reinterpret_cast<void**>(&ss->host_ctl), sizeof(Ctl))) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&ss->ev, hipEventDisableTiming)) != hipSuccess)
+    return undo(fail(DOBFS_EDEVICE, "session host state", e));
+  MsView m;
+  session_view(ss, &m);
+  if ((e = launch_ms_session_start(g->view(), m, g->grid, ss->stream)) != hipSuccess)
+    return undo(fail(DOBFS_EDEVICE, "session start launch", e));
+  {
+    std::lock_guard<std::mutex> lk(g->mu);
+    ++g->open_sessions;
+  }
+  *out = ss;
+  return DOBFS_OK;
+}
+
+int dobfs_session_admit(dobfs_session_t ss, int64_t root, int32_t* depth, int64_t tag) {
+  g_last_error.clear();
+  if (!ss || !depth) return fail(DOBFS_EINVAL, "session or depth is NULL");
+  if (root < 0 || root >= ss->g->n) return fail(DOBFS_ERANGE, "root outside [0, n)");
+  if (__builtin_popcountll(ss->active) + (int)ss->pending.size() >= 64) return fail(DOBFS_EBUSY, "64 queries in flight");
+  ss->pending.push_back({(int32_t)root, depth, tag});
+  return DOBFS_OK;
+}
+
+int dobfs_session_step(dobfs_session_t ss, int64_t* done_tags, int32_t cap, int32_t* n_done) {
+  g_last_error.clear();
+  if (!ss || !n_done || (cap > 0 && !done_tags) || cap < 0) return fail(DOBFS_EINVAL, "NULL argument or cap < 0");
+  *n_done = 0;
+  dobfs_graph_s* g = ss->g;
+  const hipStream_t s = ss->stream;
+  const GView gv = g->view();
+  if (!ss->pending.empty()) {
+    /* free slots: never used first, then those of ended queries (cleared
+       all at once, so that a clearing pass serves many admissions) */
+    const uint64_t free_clean = ~(ss->active | ss->dirty);
+    const int need = (int)ss->pending.size();
+    uint64_t clear = 0;
+    if (__builtin_popcountll(free_clean) < need) {
+      clear = ss->dirty;
+      ss->dirty = 0;
+    }
+    uint64_t avail = ~ss->active & ~ss->dirty;
+    MsRoots r;
+    SlotOuts outs;
+    std::memset(&r, 0, sizeof(r));
+    std::memset(&outs, 0, sizeof(outs));
+    uint64_t bits = 0;
+    for (const auto& q : ss->pending) {
+      const int b = __builtin_ctzll(avail);
+      avail &= avail - 1;
+      bits |= 1ull << b;
+      r.r[b] = q.root;
+      outs.p[b] = q.depth;
+      ss->tag[b] = q.tag;
+      DOBFS_HIP(hipMemsetAsync(q.depth, 0xff, sizeof(int32_t) * (size_t)g->n, s), "query output init");
+    }
+    ss->pending.clear();
+    ss->active |= bits;
+    MsView m;
+    session_view(ss, &m);
+    DOBFS_HIP(launch_ms_session_admit(gv, m, clear, r, outs, bits, g->grid, s), "admission launch");
+  }
+  if (ss->active) {
+    MsView m;
+    session_view(ss, &m);
+    for (int i = 0; i < ss->prm.chunk_levels; ++i)
+      DOBFS_HIP(launch_ms_level(gv, m, ss->kp, g->grid, s), "session level launch");
+    DOBFS_HIP(hipMemcpyAsync(ss->host_ctl, ss->w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "state copy");
+    DOBFS_HIP(hipEventRecord(ss->ev, s), "event record");
+    DOBFS_HIP(hipEventSynchronize(ss->ev), "session chunk");
+    ss->levels = ss->host_ctl->level;
+    const uint64_t ended = ss->active & ~ss->host_ctl->live;
+    for (uint64_t x = ended; x; x &= x - 1) ss->done.push_back(ss->tag[__builtin_ctzll(x)]);
+    ss->active &= ~ended;
+    ss->dirty |= ended;
+  }
+  const int32_t k = (int32_t)std::min<size_t>((size_t)cap, ss->done.size());
+  for (int32_t i = 0; i < k; ++i) done_tags[i] = ss->done[(size_t)i];
+  ss->done.erase(ss->done.begin(), ss->done.begin() + k);
+  *n_done = k;
+  return DOBFS_OK;
+}
+
+int dobfs_session_counts(dobfs_session_t ss, int32_t* active, int32_t* pending, int64_t* levels) {
+  if (!ss) return fail(DOBFS_EINVAL, "session is NULL");
+  if (active) *active = __builtin_popcountll(ss->active);
+  if (pending) *pending = (int32_t)ss->pending.size();
+  if (levels) *levels = ss->levels;
+  return DOBFS_OK;
+}
+
+int dobfs_session_close(dobfs_session_t ss) {
+  if (!ss) return DOBFS_OK;
+  hipError_t e = hipStreamSynchronize(ss->stream);
+  ss->w->busy = true;
+  (void)hipEventRecord(ss->w->idle, ss->stream);
+  release_workspace(ss->g, ss->w);
+  {
+    std::lock_guard<std::mutex> lk(ss->g->mu);
+    --ss->g->open_sessions;
+  }
+  dfree(ss->slot_out);
+  dfree(ss->slot_start);
+  (void)hipHostFree(ss->host_ctl);
+  (void)hipEventDestroy(ss->ev);
+  delete ss;
+  if (e != hipSuccess) return fail(DOBFS_EDEVICE, "session close", e);
   return DOBFS_OK;
 }
 

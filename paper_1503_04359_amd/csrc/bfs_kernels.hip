@@ -38,94 +38,10 @@
 #include <hip/hip_runtime.h>
 
 #include "dobfs_internal.h"
+#include "device_common.h"
 
 namespace dobfs {
 namespace {
-
-__device__ __forceinline__ int lane_id() {
-  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
-}
-
-__device__ __forceinline__ bool test_bit(const uint64_t* bm, int32_t v) {
-  return (bm[v >> 6] >> (v & 63)) & 1ull;
-}
-
-/* Single-winner claim of v's visited bit. */
-__device__ __forceinline__ bool try_claim(uint64_t* vis, int32_t v) {
-  const unsigned long long bit = 1ull << (v & 63);
-  unsigned long long* p = reinterpret_cast<unsigned long long*>(vis + (v >> 6));
-  if (*p & bit) return false;
-  return (atomicOr(p, bit) & bit) == 0ull;
-}
-
-struct Acc {
-  int64_t found, found_deg, checked, scanned;
-};
-
-__device__ __forceinline__ int64_t wave_sum(int64_t x) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
-}
-
-template <class T>
-__device__ __forceinline__ T ld_agent(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-/* End of a workgroup's share of a level kernel: its accumulators are summed
-   and handed on, and the call returns true in thread 0 of the last
-   workgroup of the grid.  Workgroups report to one of kGroups group slots
-   (one cache line each) and the last of each group forwards the group's sums
-   to the level counters, so no address sees more than gridDim/kGroups
-   atomics. */
-__device__ bool finish_block(Ctl* c, Acc a) {
-  __shared__ int64_t part[4][kBlock / kWave];
-  __shared__ int is_last;
-  const int lane = lane_id(), wv = threadIdx.x / kWave;
-  a.found = wave_sum(a.found);
-  a.found_deg = wave_sum(a.found_deg);
-  a.checked = wave_sum(a.checked);
-  a.scanned = wave_sum(a.scanned);
-  if (lane == 0) {
-    part[0][wv] = a.found;
-    part[1][wv] = a.found_deg;
-    part[2][wv] = a.checked;
-    part[3][wv] = a.scanned;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t sum[4] = {0, 0, 0, 0};
-    for (int k = 0; k < 4; ++k)
-      for (int j = 0; j < kBlock / kWave; ++j) sum[k] += part[k][j];
-    const uint32_t ng = gridDim.x < (uint32_t)kGroups ? gridDim.x : (uint32_t)kGroups;
-    const uint32_t grp = blockIdx.x % ng;
-    const uint32_t gsize = (gridDim.x - grp + ng - 1) / ng;
-    GroupSlot& gs = c->grp[grp];
-    for (int k = 0; k < 4; ++k)
-      if (sum[k]) atomicAdd(reinterpret_cast<unsigned long long*>(&gs.sum[k]), (unsigned long long)sum[k]);
-    __threadfence();
-    bool last = false;
-    if (atomicAdd(&gs.ticket, 1u) == gsize - 1) {
-      __threadfence();
-      int64_t* tot[4] = {&c->nf_next, &c->mf_next, &c->checked, &c->scanned};
-      for (int k = 0; k < 4; ++k) {
-        const int64_t v = ld_agent(&gs.sum[k]);
-        gs.sum[k] = 0;
-        if (v) atomicAdd(reinterpret_cast<unsigned long long*>(tot[k]), (unsigned long long)v);
-      }
-      gs.ticket = 0;
-      __threadfence();
-      last = atomicAdd(&c->ticket, 1u) == ng - 1;
-      if (last) {
-        c->ticket = 0;
-        __threadfence();
-      }
-    }
-    is_last = last;
-  }
-  __syncthreads();
-  return threadIdx.x == 0 && is_last;
-}
 
 __device__ __forceinline__ int random_dir(uint64_t seed, int32_t level) {
   uint64_t z = seed + (uint64_t)(level + 1) * 0x9E3779B97F4A7C15ull;
@@ -209,15 +125,6 @@ __device__ void decide(const GView& g, const WView& w, const KParams& kp) {
   c->scanned = 0;
   c->huge_pack = 0ull;
   c->q_fill = 0;
-}
-
-/* Inclusive prefix sum over the wavefront. */
-__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  return x;
 }
 
 /* Writes the labels of a newly reached vertex: the caller's depth/parent
@@ -308,15 +215,6 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
       }
     }
   }
-}
-
-/* Owner lane of concatenated position p (first lane whose inclusive end
-   exceeds p; incl is non-decreasing across lanes). */
-__device__ __forceinline__ int owner_of(int incl, int p) {
-  int lo = 0;
-  for (int step = kWave / 2; step > 0; step >>= 1)
-    if (__shfl(incl, lo + step - 1) <= p) lo += step;
-  return lo < kWave ? lo : kWave - 1;
 }
 
 /* One 64-entry chunk [c0, c0+64) of a bottom-up round: this lane's slice of
@@ -575,15 +473,32 @@ __global__ void __launch_bounds__(kBlock) k_init_fill(GView g, WView w) {
   }
 }
 
-__global__ void k_init_root(GView g, WView w, int32_t root_caller, int32_t first_dir) {
+/* Seeds the traversal from one or more roots (caller IDs): roots[i] for
+   i < nroots, or root0 when roots is NULL.  A root given twice is seeded
+   once.  One workgroup. */
+__global__ void __launch_bounds__(kBlock) k_init_roots(GView g, WView w, const int32_t* roots, int32_t nroots,
+                                                     int32_t root0, int32_t first_dir) {
+  __shared__ int32_t s_cnt;
+  __shared__ int64_t s_deg[kBlock / kWave];
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  int64_t dsum = 0;
+  for (int32_t i = threadIdx.x; i < nroots; i += blockDim.x) {
+    const int32_t rc = roots ? roots[i] : root0;
+    const int32_t v = g.old2new ? g.old2new[rc] : rc;
+    const unsigned long long bit = 1ull << (v & 63);
+    if (atomicOr(reinterpret_cast<unsigned long long*>(w.fr0 + (v >> 6)), bit) & bit) continue;
+    atomicOr(reinterpret_cast<unsigned long long*>(w.vis + (v >> 6)), bit);
+    store_labels(w, v, 0, v);
+    w.q0[atomicAdd(&s_cnt, 1)] = v;
+    dsum += g.off[v + 1] - g.off[v];
+  }
+  dsum = wave_sum(dsum);
+  if (lane_id() == 0) s_deg[threadIdx.x / kWave] = dsum;
+  __syncthreads();
   if (threadIdx.x != 0) return;
-  const int32_t root = g.old2new ? g.old2new[root_caller] : root_caller;
-  const uint64_t bit = 1ull << (root & 63);
-  w.vis[root >> 6] |= bit;
-  w.fr0[root >> 6] |= bit;
-  store_labels(w, root, 0, root);
-  w.q0[0] = root;
-  const int64_t dr = g.off[root + 1] - g.off[root];
+  int64_t dr = 0;
+  for (int j = 0; j < kBlock / kWave; ++j) dr += s_deg[j];
   Ctl* c = w.ctl;
   c->level = 0;
   c->dir = first_dir;
@@ -593,7 +508,7 @@ __global__ void k_init_root(GView g, WView w, int32_t root_caller, int32_t first
   c->bu_phases = first_dir == kDirBU ? 1 : 0;
   c->levels = 0;
   c->log_len = 0;
-  c->n_f = 1;
+  c->n_f = s_cnt;
   c->m_f = dr;
   c->m_u = g.m - dr;
   c->nf_next = 0;
@@ -602,10 +517,20 @@ __global__ void k_init_root(GView g, WView w, int32_t root_caller, int32_t first
   c->scanned = 0;
   c->huge_pack = 0ull;
   c->q_fill = 0;
-  c->reached = 1;
+  c->reached = s_cnt;
   c->reached_deg = dr;
   c->checked_total = 0;
   c->t_begin = wall_clock64();
+}
+
+/* Relabelled multi-root runs: every root's own labels (a degree-0 root is
+   not covered by the finalize kernel's single-root rule). */
+__global__ void k_fix_roots(WView w, const int32_t* roots, int32_t nroots) {
+  for (int32_t i = threadIdx.x; i < nroots; i += blockDim.x) {
+    const int32_t rc = roots[i];
+    w.depth[rc] = 0;
+    if (w.parent) w.parent[rc] = rc;
+  }
 }
 
 /* Relabelled graphs: caller-label outputs from the packed internal words.
@@ -646,10 +571,15 @@ hipError_t level_grid(int* grid) {
   return hipSuccess;
 }
 
-hipError_t launch_init(const GView& g, const WView& w, int64_t root, int32_t first_dir, int grid,
-                       hipStream_t s) {
+hipError_t launch_init(const GView& g, const WView& w, const int32_t* roots, int32_t nroots, int64_t root0,
+                       int32_t first_dir, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_init_fill, dim3(grid), dim3(kBlock), 0, s, g, w);
-  hipLaunchKernelGGL(k_init_root, dim3(1), dim3(kWave), 0, s, g, w, (int32_t)root, first_dir);
+  hipLaunchKernelGGL(k_init_roots, dim3(1), dim3(kBlock), 0, s, g, w, roots, nroots, (int32_t)root0, first_dir);
+  return hipGetLastError();
+}
+
+hipError_t launch_fix_roots(const WView& w, const int32_t* roots, int32_t nroots, hipStream_t s) {
+  hipLaunchKernelGGL(k_fix_roots, dim3(1), dim3(kBlock), 0, s, w, roots, nroots);
   return hipGetLastError();
 }
 

@@ -1,0 +1,131 @@
+/*
+ * Wavefront and workgroup helpers shared by the traversal kernels (wave64,
+ * gfx950).
+ */
+#ifndef DOBFS_DEVICE_COMMON_H
+#define DOBFS_DEVICE_COMMON_H
+
+#include <hip/hip_runtime.h>
+
+#include "dobfs_internal.h"
+
+namespace dobfs {
+namespace {
+
+__device__ __forceinline__ int lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
+}
+
+__device__ __forceinline__ bool test_bit(const uint64_t* bm, int32_t v) {
+  return (bm[v >> 6] >> (v & 63)) & 1ull;
+}
+
+/* Single-winner claim of v's visited bit. */
+__device__ __forceinline__ bool try_claim(uint64_t* vis, int32_t v) {
+  const unsigned long long bit = 1ull << (v & 63);
+  unsigned long long* p = reinterpret_cast<unsigned long long*>(vis + (v >> 6));
+  if (*p & bit) return false;
+  return (atomicOr(p, bit) & bit) == 0ull;
+}
+
+struct Acc {
+  int64_t found, found_deg, checked, scanned;
+  unsigned long long bits;  /* batched traversals: slots that found vertices */
+};
+
+__device__ __forceinline__ int64_t wave_sum(int64_t x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+template <class T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+/* End of a workgroup's share of a level kernel: its accumulators are summed
+   and handed on, and the call returns true in thread 0 of the last
+   workgroup of the grid.  Workgroups report to one of kGroups group slots
+   (one cache line each) and the last of each group forwards the group's sums
+   to the level counters, so no address sees more than gridDim/kGroups
+   atomics. */
+__device__ bool finish_block(Ctl* c, Acc a) {
+  __shared__ int64_t part[4][kBlock / kWave];
+  __shared__ unsigned long long bpart[kBlock / kWave];
+  __shared__ int is_last;
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  for (int o = 32; o > 0; o >>= 1) a.bits |= __shfl_xor(a.bits, o);
+  a.found = wave_sum(a.found);
+  a.found_deg = wave_sum(a.found_deg);
+  a.checked = wave_sum(a.checked);
+  a.scanned = wave_sum(a.scanned);
+  if (lane == 0) {
+    part[0][wv] = a.found;
+    part[1][wv] = a.found_deg;
+    part[2][wv] = a.checked;
+    part[3][wv] = a.scanned;
+    bpart[wv] = a.bits;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t sum[4] = {0, 0, 0, 0};
+    unsigned long long bits = 0ull;
+    for (int k = 0; k < 4; ++k)
+      for (int j = 0; j < kBlock / kWave; ++j) sum[k] += part[k][j];
+    for (int j = 0; j < kBlock / kWave; ++j) bits |= bpart[j];
+    const uint32_t ng = gridDim.x < (uint32_t)kGroups ? gridDim.x : (uint32_t)kGroups;
+    const uint32_t grp = blockIdx.x % ng;
+    const uint32_t gsize = (gridDim.x - grp + ng - 1) / ng;
+    GroupSlot& gs = c->grp[grp];
+    for (int k = 0; k < 4; ++k)
+      if (sum[k]) atomicAdd(reinterpret_cast<unsigned long long*>(&gs.sum[k]), (unsigned long long)sum[k]);
+    if (bits) atomicOr(&gs.bits, bits);
+    __threadfence();
+    bool last = false;
+    if (atomicAdd(&gs.ticket, 1u) == gsize - 1) {
+      __threadfence();
+      int64_t* tot[4] = {&c->nf_next, &c->mf_next, &c->checked, &c->scanned};
+      for (int k = 0; k < 4; ++k) {
+        const int64_t v = ld_agent(&gs.sum[k]);
+        gs.sum[k] = 0;
+        if (v) atomicAdd(reinterpret_cast<unsigned long long*>(tot[k]), (unsigned long long)v);
+      }
+      const unsigned long long gb = ld_agent(&gs.bits);
+      gs.bits = 0ull;
+      if (gb) atomicOr(&c->live_next, gb);
+      gs.ticket = 0;
+      __threadfence();
+      last = atomicAdd(&c->ticket, 1u) == ng - 1;
+      if (last) {
+        c->ticket = 0;
+        __threadfence();
+      }
+    }
+    is_last = last;
+  }
+  __syncthreads();
+  return threadIdx.x == 0 && is_last;
+}
+
+/* Inclusive prefix sum over the wavefront. */
+__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+/* Owner lane of concatenated position p (first lane whose inclusive end
+   exceeds p; incl is non-decreasing across lanes). */
+__device__ __forceinline__ int owner_of(int incl, int p) {
+  int lo = 0;
+  for (int step = kWave / 2; step > 0; step >>= 1)
+    if (__shfl(incl, lo + step - 1) <= p) lo += step;
+  return lo < kWave ? lo : kWave - 1;
+}
+
+}  // namespace
+}  // namespace dobfs
+
+#endif

@@ -43,6 +43,8 @@ constexpr int kDirBU = 1;
 constexpr int kAuxNone = 0;
 constexpr int kAuxHuge = 1;          /* split top-down vertices still to expand */
 constexpr int kAuxToQueue = 2;       /* next level top-down: bitmap to queue */
+constexpr int kAuxMsUpdate = 3;      /* batched push level: fold nxt into the frontier */
+constexpr int kMsTake = 256;         /* batched push: entries per row and round */
 
 constexpr int kGroups = 16;
 constexpr int kMaxSeg = 72;          /* degree classes of int64 degrees, plus one */
@@ -51,8 +53,9 @@ constexpr int kFinGrid = 1024;       /* finalize workgroups (4 per CU) */       
 
 struct GroupSlot {
   int64_t sum[4];
+  unsigned long long bits; /* OR of the batched slots that found vertices */
   uint32_t ticket;
-  uint32_t pad[23];     /* one 128-byte cache line per group */
+  uint32_t pad[21];     /* one 128-byte cache line per group */
 };
 
 /* Level state, advanced on the device by the last workgroup of each level. */
@@ -80,6 +83,11 @@ struct Ctl {
   /* totals */
   int64_t reached, reached_deg, checked_total;
   uint64_t t_begin;
+  /* batched sessions */
+  unsigned long long live_next; /* slots that found vertices in this level   */
+  unsigned long long live;      /* ... in the last completed level           */
+  int32_t active_slots;         /* slots being served (direction rule)       */
+  int32_t pad3;
   GroupSlot grp[kGroups]; /* zero between kernels */
 };
 
@@ -122,9 +130,46 @@ struct WView {
   int32_t pad;
 };
 
+/* Batched traversal state (msbfs.hip): bit b of each mask = root slot b. */
+struct MsView {
+  uint64_t* visit;
+  uint64_t* cur0;
+  uint64_t* cur1;
+  uint64_t* nxt;
+  int32_t* out;         /* caller's depths, root-major [k][n], caller IDs      */
+  int32_t* internal;    /* relabelled graphs: [v][k] in internal IDs, else 0 */
+  int32_t k;
+  int32_t pad;
+  uint64_t full;        /* the k low bits                                     */
+  Ctl* ctl;
+  dobfs_level_rec* log;
+  int32_t log_cap;
+  int32_t session;      /* 1: per-slot outputs below, slots join and leave */
+  int32_t** slot_out;   /* session: device table, depth array of each slot  */
+  int32_t* slot_start;  /* session: device table, level each slot joined at */
+};
+
+struct MsRoots {
+  int32_t r[64];        /* caller IDs */
+};
+
+hipError_t launch_ms_init(const GView& g, const MsView& m, const MsRoots& r, int grid, hipStream_t s);
+hipError_t launch_ms_level(const GView& g, const MsView& m, const KParams& kp, int grid, hipStream_t s);
+hipError_t launch_ms_finalize(const GView& g, const MsView& m, const MsRoots& r, int grid, hipStream_t s);
+/* Session: empty masks and an idle control block. */
+hipError_t launch_ms_session_start(const GView& g, const MsView& m, int grid, hipStream_t s);
+/* Session admission: forget the slots in clear_bits, then seed the slots in
+   new_bits with roots r.r[b] (caller IDs) and outputs outs.p[b]. */
+struct SlotOuts {
+  int32_t* p[64];
+};
+hipError_t launch_ms_session_admit(const GView& g, const MsView& m, unsigned long long clear_bits, const MsRoots& r,
+                                   const SlotOuts& outs, unsigned long long new_bits, int grid, hipStream_t s);
+
 /* Kernel launchers (bfs_kernels.hip). */
-hipError_t launch_init(const GView& g, const WView& w, int64_t root, int32_t first_dir, int grid,
-                       hipStream_t s);
+hipError_t launch_init(const GView& g, const WView& w, const int32_t* roots, int32_t nroots, int64_t root0,
+                       int32_t first_dir, int grid, hipStream_t s);
+hipError_t launch_fix_roots(const WView& w, const int32_t* roots, int32_t nroots, hipStream_t s);
 hipError_t launch_level(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s);
 hipError_t launch_aux(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s);
 hipError_t launch_finalize(const GView& g, const WView& w, int64_t root, int grid, hipStream_t s);
@@ -140,6 +185,8 @@ int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m
 /* Graph preparation launchers (graph_kernels.hip). */
 hipError_t launch_graph_scan(const int64_t* off, int64_t n, uint64_t* iso, int64_t* counters,
                              int grid, hipStream_t s);
+hipError_t launch_pack_copy(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int64_t nbase, int64_t mbase,
+                            bool src_device, int64_t* uoff, int32_t* uidx, hipStream_t s);
 hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int symmetry,
                            int32_t* bad, int grid, hipStream_t s);
 

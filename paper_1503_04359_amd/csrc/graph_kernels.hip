@@ -3,6 +3,8 @@
  */
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dobfs_internal.h"
 
 namespace dobfs {
@@ -96,7 +98,57 @@ __global__ void __launch_bounds__(kBlock) k_validate_symmetry(const int64_t* off
   }
 }
 
+__global__ void k_shift_i64(int64_t* dst, const int64_t* src, int64_t count, int64_t add) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += nth) dst[i] = src[i] + add;
+}
+
+__global__ void k_shift_i32(int32_t* dst, const int32_t* src, int64_t count, int32_t add) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += nth) dst[i] = src[i] + add;
+}
+
 }  // namespace
+
+/* Graph i of a pack into the union CSR: offsets shifted by the entries
+   before it, neighbour IDs by the vertices before it.  Host sources are
+   staged through a device buffer. */
+hipError_t launch_pack_copy(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int64_t nbase, int64_t mbase,
+                            bool src_device, int64_t* uoff, int32_t* uidx, hipStream_t s) {
+  const int64_t* doff = off;
+  const int32_t* didx = idx;
+  int64_t* t_off = nullptr;
+  int32_t* t_idx = nullptr;
+  hipError_t e = hipSuccess;
+  if (!src_device) {
+    if ((e = hipMalloc(&t_off, sizeof(int64_t) * (size_t)(n + 1))) != hipSuccess) return e;
+    if ((e = hipMalloc(&t_idx, sizeof(int32_t) * (size_t)(m > 0 ? m : 1))) != hipSuccess) {
+      (void)hipFree(t_off);
+      return e;
+    }
+    if ((e = hipMemcpyAsync(t_off, off, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (m > 0 && (e = hipMemcpyAsync(t_idx, idx, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s)) != hipSuccess)) {
+      (void)hipFree(t_off);
+      (void)hipFree(t_idx);
+      return e;
+    }
+    doff = t_off;
+    didx = t_idx;
+  }
+  const unsigned blocks_o = (unsigned)std::min<int64_t>((n + 1 + 255) / 256, 4096);
+  const unsigned blocks_i = (unsigned)std::min<int64_t>((m + 255) / 256 > 0 ? (m + 255) / 256 : 1, 4096);
+  /* the last graph's offsets[n] lands on the union's offsets[N] */
+  hipLaunchKernelGGL(k_shift_i64, dim3(blocks_o), dim3(256), 0, s, uoff + nbase, doff, n + 1, mbase);
+  if (m > 0) hipLaunchKernelGGL(k_shift_i32, dim3(blocks_i), dim3(256), 0, s, uidx + mbase, didx, m, (int32_t)nbase);
+  e = hipGetLastError();
+  if (!src_device) {
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(t_off);
+    (void)hipFree(t_idx);
+    if (e == hipSuccess) e = e2;
+  }
+  return e;
+}
 
 hipError_t launch_graph_scan(const int64_t* off, int64_t n, uint64_t* iso, int64_t* counters, int grid,
                              hipStream_t s) {
