@@ -672,8 +672,10 @@ int dobfs_batch_submit(dobfs_graph_t g, const int64_t* roots, int32_t k, int32_t
   m.session = 0;
   m.slot_out = nullptr;
   m.slot_start = nullptr;
+  m.split_u = w->huge_u;
+  m.split_base = w->huge_base;
   const KParams kp = to_kparams(prm);
-  DOBFS_HIP(launch_ms_init(gv, m, r, g->grid, s), "batch init launch");
+  DOBFS_HIP(launch_ms_init(gv, m, r, first_direction(prm) == kDirBU ? 1 : 0, g->grid, s), "batch init launch");
   auto level = [&](int64_t) -> int {
     DOBFS_HIP(launch_ms_level(gv, m, kp, g->grid, s), "batch level launch");
     return DOBFS_OK;
@@ -777,6 +779,8 @@ static int session_view(dobfs_session_s* ss, MsView* m) {
   m->session = 1;
   m->slot_out = ss->slot_out;
   m->slot_start = ss->slot_start;
+  m->split_u = w->huge_u;
+  m->split_base = w->huge_base;
   return DOBFS_OK;
 }
 
@@ -871,7 +875,9 @@ int dobfs_session_step(dobfs_session_t ss, int64_t* done_tags, int32_t cap, int3
     ss->active |= bits;
     MsView m;
     session_view(ss, &m);
-    DOBFS_HIP(launch_ms_session_admit(gv, m, clear, r, outs, bits, g->grid, s), "admission launch");
+    DOBFS_HIP(launch_ms_session_admit(gv, m, clear, r, outs, bits,
+                                      ss->prm.policy == DOBFS_POLICY_FORCED_BU ? 1 : 0, g->grid, s),
+              "admission launch");
   }
   if (ss->active) {
     MsView m;

@@ -43,7 +43,11 @@ constexpr int kDirBU = 1;
 constexpr int kAuxNone = 0;
 constexpr int kAuxHuge = 1;          /* split top-down vertices still to expand */
 constexpr int kAuxToQueue = 2;       /* next level top-down: bitmap to queue */
-constexpr int kAuxMsUpdate = 3;      /* batched push level: fold nxt into the frontier */
+constexpr int kAuxMsUpdate = 3;      /* batched level: fold nxt into the frontier     */
+constexpr int kAuxMsSplit = 4;       /* batched level: chunks of split vertices left  */
+constexpr int kMsPushSplit = 256;    /* batched push: degree above which a vertex is split */
+constexpr int kMsPullSplit = 2048;   /* batched pull: degree above which a vertex may be split */
+constexpr int kMsPullProbe = 512;    /* batched pull: entries such a vertex scans before it is split */
 constexpr int kMsTake = 256;         /* batched push: entries per row and round */
 
 constexpr int kGroups = 16;
@@ -59,6 +63,18 @@ struct GroupSlot {
 };
 
 /* Level state, advanced on the device by the last workgroup of each level. */
+/* Per-slot counters of a batched traversal, for the per-slot switching
+   rule.  Frontier edges are estimated: each wavefront credits a slot with
+   its count of new vertices times their mean degree. */
+struct SlotStat {
+  int64_t nf;                    /* frontier vertices of the slot, level L  */
+  int64_t mf;                    /* estimated frontier edges                */
+  int64_t mu;                    /* estimated edges not yet explored        */
+  unsigned long long nf_next;    /* accumulators of the level in progress   */
+  unsigned long long mf_next;
+  int64_t pad[3];
+};
+
 struct Ctl {
   int32_t level;        /* L: frontier = vertices of depth L              */
   int32_t dir;          /* direction of level L                           */
@@ -86,9 +102,11 @@ struct Ctl {
   /* batched sessions */
   unsigned long long live_next; /* slots that found vertices in this level   */
   unsigned long long live;      /* ... in the last completed level           */
-  int32_t active_slots;         /* slots being served (direction rule)       */
+  int32_t active_slots;         /* slots being served                        */
   int32_t pad3;
+  unsigned long long pull_mask; /* batched: slots pulled (bottom-up) in level L */
   GroupSlot grp[kGroups]; /* zero between kernels */
+  SlotStat slot[64];      /* batched: per-slot counters                      */
 };
 
 struct KParams {
@@ -137,7 +155,7 @@ struct MsView {
   uint64_t* cur1;
   uint64_t* nxt;
   int32_t* out;         /* caller's depths, root-major [k][n], caller IDs      */
-  int32_t* internal;    /* relabelled graphs: [v][k] in internal IDs, else 0 */
+  int32_t* internal;    /* relabelled graphs: [k][n_nonisolated], internal IDs */
   int32_t k;
   int32_t pad;
   uint64_t full;        /* the k low bits                                     */
@@ -147,13 +165,15 @@ struct MsView {
   int32_t session;      /* 1: per-slot outputs below, slots join and leave */
   int32_t** slot_out;   /* session: device table, depth array of each slot  */
   int32_t* slot_start;  /* session: device table, level each slot joined at */
+  int32_t* split_u;     /* split vertices of the running level (list entries) */
+  uint32_t* split_base; /* first chunk number of each entry, increasing      */
 };
 
 struct MsRoots {
   int32_t r[64];        /* caller IDs */
 };
 
-hipError_t launch_ms_init(const GView& g, const MsView& m, const MsRoots& r, int grid, hipStream_t s);
+hipError_t launch_ms_init(const GView& g, const MsView& m, const MsRoots& r, int first_pull, int grid, hipStream_t s);
 hipError_t launch_ms_level(const GView& g, const MsView& m, const KParams& kp, int grid, hipStream_t s);
 hipError_t launch_ms_finalize(const GView& g, const MsView& m, const MsRoots& r, int grid, hipStream_t s);
 /* Session: empty masks and an idle control block. */
@@ -164,7 +184,8 @@ struct SlotOuts {
   int32_t* p[64];
 };
 hipError_t launch_ms_session_admit(const GView& g, const MsView& m, unsigned long long clear_bits, const MsRoots& r,
-                                   const SlotOuts& outs, unsigned long long new_bits, int grid, hipStream_t s);
+                                   const SlotOuts& outs, unsigned long long new_bits, int first_pull, int grid,
+                                   hipStream_t s);
 
 /* Kernel launchers (bfs_kernels.hip). */
 hipError_t launch_init(const GView& g, const WView& w, const int32_t* roots, int32_t nroots, int64_t root0,

@@ -44,6 +44,8 @@ def test_batch_64_roots_kronecker(dobfs):
     roots = gg.sample_roots(g, 64, seed=5)
     for pol in ("edge", "td", "bu"):
         _check(dobfs, g, roots, params=dobfs.make_params(pol), label=f"kron14/{pol}")
+    for seed in (1, 2, 3):  # a random direction per slot and level: mixed push/pull levels
+        _check(dobfs, g, roots, params=dobfs.make_params("random", seed=seed), label=f"kron14/random{seed}")
 
 
 def test_batch_relabelled(dobfs):
@@ -51,6 +53,7 @@ def test_batch_relabelled(dobfs):
     roots = gg.sample_roots(g, 64, seed=6)
     for pol in ("edge", "bu"):
         _check(dobfs, g, roots, params=dobfs.make_params(pol), reindex=True, label=f"kron15/{pol}/reindex")
+    _check(dobfs, g, roots, params=dobfs.make_params("random", seed=9), reindex=True, label="kron15/random/reindex")
 
 
 def test_batch_small_k_duplicates_and_isolated(dobfs):
@@ -65,9 +68,12 @@ def test_batch_many_levels_and_heavy(dobfs):
     g = gg.chung_lu(20000, gamma=2.2, avg_deg=8.0, max_deg=2000.0, n_tails=4, tail_len=120, seed=9)
     roots = gg.sample_roots(g, 33, seed=2)
     _check(dobfs, g, roots, label="chung-lu+tails")
+    _check(dobfs, g, roots, params=dobfs.make_params("random", seed=4), label="chung-lu+tails/random")
     g = gg.star(5000)
     _check(dobfs, g, [0, 1, 4999, 17], params=dobfs.make_params("bu", bu_heavy_cut=64), label="star/bu")
     _check(dobfs, g, [0, 1, 4999, 17], params=dobfs.make_params("td"), label="star/td")
+    for seed in range(4):  # the hub is split in push and in pull levels
+        _check(dobfs, g, [0, 1, 4999, 17, 2, 3], params=dobfs.make_params("random", seed=seed), label="star/random")
 
 
 def test_batch_matches_single_runs(dobfs):

@@ -67,7 +67,7 @@ def test_session_staggered_queries_kronecker(dobfs, reindex):
         assert np.array_equal(res[t], exp[int(r)]), (t, int(r))
 
 
-@pytest.mark.parametrize("policy", ["td", "bu", "edge"])
+@pytest.mark.parametrize("policy", ["td", "bu", "edge", "random"])
 def test_session_long_paths_and_isolated(dobfs, policy):
     """Queries on a graph with long tails, a separate component and isolated
     vertices; some roots isolated.  One level per chunk so queries join at
