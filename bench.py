@@ -65,7 +65,7 @@ def kernel_source_digest() -> str:
     reported for the kernel it was measured on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("bfs_kernels.hip", "dobfs_internal.h"):
+    for f in ("bfs_kernels.hip", "device_common.h", "dobfs_internal.h"):
         with open(os.path.join(ROOT, "paper_1503_04359_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -338,8 +338,51 @@ def bench_serve(args) -> dict:
             "rates": results}
 
 
+def traffic_from_counters(fetch_csv: str, write_csv: str, probe_bytes: int, key: str, out_path: str) -> dict:
+    """HBM bytes per level-kernel launch from two rocprofv3 --pmc runs of the
+    same command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+    scaled by what the counter reads for the copy probe, whose kernel reads
+    and writes `probe_bytes` bytes."""
+    import csv
+
+    def load(path, counter):
+        probe, level = [], []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                name, val = r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0
+                if "CUDAFunctorOnSelf_add" in name:
+                    probe.append(val)
+                elif "k_level(" in name:
+                    level.append(val)
+        if not probe or not level:
+            raise ValueError(f"{path}: no copy-probe or level-kernel dispatches for {counter}")
+        return probe[0], level
+
+    pf, lf = load(fetch_csv, "FETCH_SIZE")
+    pw, lw = load(write_csv, "WRITE_SIZE")
+    kf, kw = probe_bytes / pf, probe_bytes / pw
+    per_launch = (sum(lf) * kf + sum(lw) * kw) / len(lf)
+    ent = {"kernel": "k_level", "source_sha256": kernel_source_digest(), "bytes_per_launch": round(per_launch),
+           "fetch_factor": round(kf, 4), "write_factor": round(kw, 4), "launches": len(lf),
+           "fetch_bytes_per_launch": round(sum(lf) * kf / len(lf)), "write_bytes_per_launch": round(sum(lw) * kw / len(lw))}
+    data = {}
+    if os.path.exists(out_path):
+        with open(out_path) as f:
+            data = json.load(f)
+    data[key] = ent
+    with open(out_path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+        f.write("\n")
+    return ent
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter CSVs of this bench "
+                         "(run with --copy-probe) and exit")
     ap.add_argument("--mode", choices=("single", "batch", "pack", "serve"), default="single")
     ap.add_argument("--pack-graphs", type=int, default=2000)
     ap.add_argument("--serve-rates", default="500,2000,8000")
@@ -364,6 +407,16 @@ def main() -> int:
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="first run a plain device copy kernel over this many GiB (counter calibration)")
     args = ap.parse_args()
+
+    if args.traffic_from:
+        key = f"kron-s{args.scale}-ef{args.edgefactor}-seed{args.seed}/{args.policy}/reindex-{args.reindex}"
+        nbytes = int(args.copy_probe * (1 << 30)) // 4 * 4
+        if nbytes <= 0:
+            print("--traffic-from needs the --copy-probe size the counters were taken with", file=sys.stderr)
+            return 2
+        print(json.dumps(traffic_from_counters(args.traffic_from[0], args.traffic_from[1], nbytes, key,
+                                               args.traffic)))
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "

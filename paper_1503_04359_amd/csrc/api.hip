@@ -613,6 +613,8 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
   if (!stats) return DOBFS_OK;
   std::vector<float> kms;
   if (timed) {
+    /* the lookahead chunk may still be running: wait before reading its events */
+    DOBFS_HIP(hipEventSynchronize(w->idle), "timing wait");
     kms.resize((size_t)launches);
     for (int64_t i = 0; i < launches; ++i)
       DOBFS_HIP(hipEventElapsedTime(&kms[(size_t)i], w->tev[2 * i], w->tev[2 * i + 1]), "timing");
