@@ -537,22 +537,56 @@ __global__ void k_fix_roots(WView w, const int32_t* roots, int32_t nroots) {
    Caller vertex x has internal label v = old2new[x]; v was reached exactly
    when it is the root or its visited bit is set and v < n_nonisolated
    (degree-0 vertices start visited but are never reached).  Parents are
-   mapped back through new2old. */
+   mapped back through new2old.  Each thread takes kFinUnroll caller IDs a
+   workgroup apart and issues each round of loads for all of them before
+   using any, so every lane keeps several independent gathers in flight;
+   the streamed arrays (old2new, the outputs) bypass the caches' retention. */
+constexpr int kFinUnroll = 8;
+
 __global__ void __launch_bounds__(kBlock) k_finalize(GView g, WView w, int32_t root_caller) {
-  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < g.n; x += nth) {
-    const int32_t v = g.old2new[x];
-    int32_t d = -1, p = -1;
-    if (x == root_caller) {
-      d = 0;
-      p = root_caller;
-    } else if ((int64_t)v < g.n_nonisolated && ((w.vis[v >> 6] >> (v & 63)) & 1ull)) {
-      const uint64_t rec = (uint64_t)w.packed[v];
-      d = (int32_t)(uint32_t)(rec & 0xFFFFFFFFull);
-      p = g.new2old[(int32_t)(uint32_t)(rec >> 32)];
+  /* Workgroups are dealt to the kXcds dies round-robin.  Each die sweeps
+     its own contiguous eighth of the caller range, so the runs of
+     consecutive internal IDs that a range gathers from stay in one die's
+     L2 while its workgroups move along them. */
+  const int64_t nn = g.n_nonisolated;
+  const int xcd = (int)(blockIdx.x % kXcds);
+  const int64_t per_xcd = (int64_t)(gridDim.x / kXcds);
+  const int64_t local = (int64_t)(blockIdx.x / kXcds);
+  const int64_t span = (int64_t)blockDim.x * kFinUnroll;
+  const int64_t part = ((g.n + kXcds - 1) / kXcds + span - 1) / span * span;
+  const int64_t lo = (int64_t)xcd * part, hi = min(g.n, lo + part);
+  for (int64_t base = lo + local * span + threadIdx.x; base < hi; base += per_xcd * span) {
+    int32_t v[kFinUnroll];
+#pragma unroll
+    for (int j = 0; j < kFinUnroll; ++j) {
+      const int64_t x = base + (int64_t)j * blockDim.x;
+      v[j] = x < hi ? __builtin_nontemporal_load(g.old2new + x) : 0x7FFFFFFF;
     }
-    w.depth[x] = d;
-    if (w.parent) w.parent[x] = p;
+    uint64_t word[kFinUnroll], rec[kFinUnroll];
+#pragma unroll
+    for (int j = 0; j < kFinUnroll; ++j) {
+      const bool in = (int64_t)v[j] < nn;
+      word[j] = in ? w.vis[v[j] >> 6] : 0ull;
+      rec[j] = in ? (uint64_t)w.packed[v[j]] : 0ull;
+    }
+    int32_t d[kFinUnroll], p[kFinUnroll];
+#pragma unroll
+    for (int j = 0; j < kFinUnroll; ++j) {
+      const bool hit = (word[j] >> (v[j] & 63)) & 1ull;
+      d[j] = hit ? (int32_t)(uint32_t)(rec[j] & 0xFFFFFFFFull) : -1;
+      p[j] = hit ? g.new2old[(int32_t)(uint32_t)(rec[j] >> 32)] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < kFinUnroll; ++j) {
+      const int64_t x = base + (int64_t)j * blockDim.x;
+      if (x >= hi) continue;
+      if (x == root_caller) {
+        d[j] = 0;
+        p[j] = root_caller;
+      }
+      __builtin_nontemporal_store(d[j], w.depth + x);
+      if (w.parent) __builtin_nontemporal_store(p[j], w.parent + x);
+    }
   }
 }
 
@@ -589,7 +623,7 @@ hipError_t launch_level(const GView& g, const WView& w, const KParams& kp, int g
 }
 
 hipError_t launch_finalize(const GView& g, const WView& w, int64_t root, int grid, hipStream_t s) {
-  const int64_t blocks = grid;
+  const int64_t blocks = grid < kXcds ? kXcds : grid / kXcds * kXcds; /* whole workgroups per die */
   hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(kBlock), 0, s, g, w, (int32_t)root);
   return hipGetLastError();
 }

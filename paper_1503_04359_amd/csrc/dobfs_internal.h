@@ -51,6 +51,7 @@ constexpr int kMsPullProbe = 512;    /* batched pull: entries such a vertex scan
 constexpr int kMsTake = 256;         /* batched push: entries per row and round */
 
 constexpr int kGroups = 16;
+constexpr int kXcds = 8;             /* dies (XCDs) of an MI355X; workgroups are dealt round-robin */
 constexpr int kMaxSeg = 72;          /* degree classes of int64 degrees, plus one */
 constexpr int kFinBlock = 4096;      /* minimum caller IDs per finalize workgroup */
 constexpr int kFinGrid = 1024;       /* finalize workgroups (4 per CU) */          /* completion groups per kernel (see finish_block) */

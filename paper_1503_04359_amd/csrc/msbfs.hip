@@ -636,7 +636,7 @@ __global__ void __launch_bounds__(kBlock) k_ms_finalize(GView g, MsView m, MsRoo
 #pragma unroll
     for (int j = 0; j < kFinPer; ++j) {
       const int64_t x = x0 + (int64_t)j * kBlock + threadIdx.x;
-      v[j] = x < g.n ? g.old2new[x] : -1;
+      v[j] = x < g.n ? __builtin_nontemporal_load(g.old2new + x) : -1;
       vis[j] = (v[j] >= 0 && (int64_t)v[j] < nn) ? m.visit[v[j]] : 0ull;
     }
     for (int b = 0; b < m.k; ++b) {
@@ -648,7 +648,7 @@ __global__ void __launch_bounds__(kBlock) k_ms_finalize(GView g, MsView m, MsRoo
         int32_t d;
         if ((int64_t)v[j] < nn) d = ((vis[j] >> b) & 1ull) ? m.internal[(int64_t)b * nn + v[j]] : -1;
         else d = (rb == (int32_t)x) ? 0 : -1;
-        m.out[(int64_t)b * g.n + x] = d;
+        __builtin_nontemporal_store(d, m.out + (int64_t)b * g.n + x);
       }
     }
   }
