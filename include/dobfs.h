@@ -256,6 +256,9 @@ int dobfs_batch_submit(dobfs_graph_t g, const int64_t* roots, int32_t k, int32_t
      when nothing is admitted.
    dobfs_session_counts: *active = queries holding a slot, *pending =
      admitted but not yet joined, *levels = levels run so far.
+   dobfs_session_levels: the per-level records of the last step's chunk
+     (at most cap into recs, *n of them); dir is 0 push, 1 pull, 2 mixed;
+     kernel_ms is 0.
    dobfs_session_close: waits for the stream, forgets queries not reported
      done and releases the workspace.  NULL is accepted.
    Errors: EINVAL (NULL arguments), ERANGE, EBUSY, ENOMEM, EDEVICE. */
@@ -265,6 +268,7 @@ int dobfs_session_open(dobfs_graph_t g, const dobfs_params* p, void* stream, dob
 int dobfs_session_admit(dobfs_session_t s, int64_t root, int32_t* depth, int64_t tag);
 int dobfs_session_step(dobfs_session_t s, int64_t* done_tags, int32_t cap, int32_t* n_done);
 int dobfs_session_counts(dobfs_session_t s, int32_t* active, int32_t* pending, int64_t* levels);
+int dobfs_session_levels(dobfs_session_t s, dobfs_level_rec* recs, int32_t cap, int32_t* n);
 int dobfs_session_close(dobfs_session_t s);
 
 /* Strings for a status; valid forever. */

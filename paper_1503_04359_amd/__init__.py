@@ -35,7 +35,7 @@ POLICIES = {"edge": POLICY_EDGE, "paper": POLICY_PAPER, "td": POLICY_FORCED_TD,
 EXPORTED = ("dobfs_default_params", "dobfs_graph_upload", "dobfs_graph_free", "dobfs_graph_info",
             "dobfs_run", "dobfs_run_multi", "dobfs_batch_submit", "dobfs_pack_upload", "dobfs_pack_bases",
             "dobfs_pack_run", "dobfs_session_open", "dobfs_session_admit", "dobfs_session_step",
-            "dobfs_session_counts", "dobfs_session_close", "dobfs_strerror", "dobfs_last_error")
+            "dobfs_session_counts", "dobfs_session_levels", "dobfs_session_close", "dobfs_strerror", "dobfs_last_error")
 
 
 class DobfsError(RuntimeError):
@@ -107,6 +107,8 @@ _lib.dobfs_session_step.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.POINTER(cty
 _lib.dobfs_session_counts.restype = ctypes.c_int
 _lib.dobfs_session_counts.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(_i64)]
+_lib.dobfs_session_levels.restype = ctypes.c_int
+_lib.dobfs_session_levels.argtypes = [_vp, ctypes.POINTER(LevelRec), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
 _lib.dobfs_session_close.restype = ctypes.c_int
 _lib.dobfs_session_close.argtypes = [_vp]
 _lib.dobfs_strerror.restype = ctypes.c_char_p
@@ -369,6 +371,13 @@ class Session:
         _check(_lib.dobfs_session_counts(self._h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(lv)),
                "dobfs_session_counts")
         return a.value, p.value, lv.value
+
+    def levels(self) -> list[dict]:
+        """Per-level records of the last step's chunk."""
+        recs = (LevelRec * 1024)()
+        k = ctypes.c_int32()
+        _check(_lib.dobfs_session_levels(self._h, recs, 1024, ctypes.byref(k)), "dobfs_session_levels")
+        return [{f: getattr(recs[i], f) for f, _ in LevelRec._fields_} for i in range(k.value)]
 
     def close(self) -> None:
         if self._h:

@@ -142,6 +142,8 @@ struct dobfs_session_s {
   uint64_t active = 0;   /* slots whose query runs */
   uint64_t dirty = 0;    /* slots whose bits still mark an ended query */
   int64_t tag[64] = {};
+  int32_t root[64] = {};       /* caller ID of each slot's root */
+  int32_t* out[64] = {};       /* caller's depth array of each slot */
   struct Pending {
     int32_t root;
     int32_t* depth;
@@ -150,6 +152,7 @@ struct dobfs_session_s {
   std::vector<Pending> pending;
   std::vector<int64_t> done;  /* ended, not yet reported */
   int64_t levels = 0;
+  std::vector<dobfs_level_rec> last_log;  /* levels of the last chunk */
 };
 
 namespace {
@@ -771,13 +774,13 @@ static int session_view(dobfs_session_s* ss, MsView* m) {
   m->cur1 = w->ms_cur1;
   m->nxt = w->ms_nxt;
   m->out = nullptr;
-  m->internal = nullptr;
+  m->internal = ss->g->new2old ? w->ms_internal : nullptr;
   m->k = 64;
   m->pad = 0;
   m->full = ss->active;
   m->ctl = w->ctl;
   m->log = w->log;
-  m->log_cap = 0;
+  m->log_cap = ss->prm.chunk_levels < w->log_cap ? ss->prm.chunk_levels : w->log_cap;
   m->session = 1;
   m->slot_out = ss->slot_out;
   m->slot_start = ss->slot_start;
@@ -813,7 +816,9 @@ int dobfs_session_open(dobfs_graph_t g, const dobfs_params* p, void* stream, dob
     ss->w = nullptr;
     return undo(st);
   }
-  if ((st = ensure_ms_buffers(g, ss->w, 0)) != DOBFS_OK) return undo(st);
+  /* relabelled graphs: depths go to internal order first (one slot-major
+     row per slot), mapped to caller order when the query ends */
+  if ((st = ensure_ms_buffers(g, ss->w, 64)) != DOBFS_OK) return undo(st);
   hipError_t e;
   if ((e = dalloc(&ss->slot_out, 64)) != hipSuccess || (e = dalloc(&ss->slot_start, 64)) != hipSuccess)
     return undo(fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "session tables", e));
@@ -871,7 +876,11 @@ int dobfs_session_step(dobfs_session_t ss, int64_t* done_tags, int32_t cap, int3
       r.r[b] = q.root;
       outs.p[b] = q.depth;
       ss->tag[b] = q.tag;
-      DOBFS_HIP(hipMemsetAsync(q.depth, 0xff, sizeof(int32_t) * (size_t)g->n, s), "query output init");
+      ss->root[b] = q.root;
+      ss->out[b] = q.depth;
+      /* unrelabelled graphs write depths straight into the caller's array */
+      if (!g->new2old)
+        DOBFS_HIP(hipMemsetAsync(q.depth, 0xff, sizeof(int32_t) * (size_t)g->n, s), "query output init");
     }
     ss->pending.clear();
     ss->active |= bits;
@@ -881,16 +890,39 @@ int dobfs_session_step(dobfs_session_t ss, int64_t* done_tags, int32_t cap, int3
                                       ss->prm.policy == DOBFS_POLICY_FORCED_BU ? 1 : 0, g->grid, s),
               "admission launch");
   }
+  ss->last_log.clear();
   if (ss->active) {
     MsView m;
     session_view(ss, &m);
+    /* the log holds the levels of this chunk only */
+    DOBFS_HIP(hipMemsetAsync(&ss->w->ctl->log_len, 0, sizeof(int32_t), s), "log reset");
     for (int i = 0; i < ss->prm.chunk_levels; ++i)
       DOBFS_HIP(launch_ms_level(gv, m, ss->kp, g->grid, s), "session level launch");
     DOBFS_HIP(hipMemcpyAsync(ss->host_ctl, ss->w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "state copy");
     DOBFS_HIP(hipEventRecord(ss->ev, s), "event record");
     DOBFS_HIP(hipEventSynchronize(ss->ev), "session chunk");
     ss->levels = ss->host_ctl->level;
+    const int32_t nlog = std::min(ss->host_ctl->log_len, m.log_cap);
+    if (nlog > 0) {
+      ss->last_log.resize((size_t)nlog);
+      DOBFS_HIP(hipMemcpy(ss->last_log.data(), ss->w->log, sizeof(dobfs_level_rec) * (size_t)nlog,
+                          hipMemcpyDeviceToHost), "log copy");
+    }
     const uint64_t ended = ss->active & ~ss->host_ctl->live;
+    if (ended && g->new2old) {
+      MsRoots r;
+      SlotOuts outs;
+      std::memset(&r, 0, sizeof(r));
+      std::memset(&outs, 0, sizeof(outs));
+      for (uint64_t x = ended; x; x &= x - 1) {
+        const int b = __builtin_ctzll(x);
+        r.r[b] = ss->root[b];
+        outs.p[b] = ss->out[b];
+      }
+      DOBFS_HIP(launch_ms_session_finalize(gv, m, r, outs, ended, g->grid, s), "query finalize launch");
+      DOBFS_HIP(hipEventRecord(ss->ev, s), "event record");
+      DOBFS_HIP(hipEventSynchronize(ss->ev), "query finalize");
+    }
     for (uint64_t x = ended; x; x &= x - 1) ss->done.push_back(ss->tag[__builtin_ctzll(x)]);
     ss->active &= ~ended;
     ss->dirty |= ended;
@@ -907,6 +939,14 @@ int dobfs_session_counts(dobfs_session_t ss, int32_t* active, int32_t* pending, 
   if (active) *active = __builtin_popcountll(ss->active);
   if (pending) *pending = (int32_t)ss->pending.size();
   if (levels) *levels = ss->levels;
+  return DOBFS_OK;
+}
+
+int dobfs_session_levels(dobfs_session_t ss, dobfs_level_rec* recs, int32_t cap, int32_t* n) {
+  if (!ss || !n || (cap > 0 && !recs)) return fail(DOBFS_EINVAL, "NULL argument");
+  const int32_t k = (int32_t)std::min<size_t>((size_t)std::max(cap, 0), ss->last_log.size());
+  for (int32_t i = 0; i < k; ++i) recs[i] = ss->last_log[(size_t)i];
+  *n = k;
   return DOBFS_OK;
 }
 

@@ -177,16 +177,22 @@ struct MsRoots {
 hipError_t launch_ms_init(const GView& g, const MsView& m, const MsRoots& r, int first_pull, int grid, hipStream_t s);
 hipError_t launch_ms_level(const GView& g, const MsView& m, const KParams& kp, int grid, hipStream_t s);
 hipError_t launch_ms_finalize(const GView& g, const MsView& m, const MsRoots& r, int grid, hipStream_t s);
+/* Output array of each slot of a session admission or finalize. */
+struct SlotOuts {
+  int32_t* p[64];
+};
+
 /* Session: empty masks and an idle control block. */
 hipError_t launch_ms_session_start(const GView& g, const MsView& m, int grid, hipStream_t s);
 /* Session admission: forget the slots in clear_bits, then seed the slots in
    new_bits with roots r.r[b] (caller IDs) and outputs outs.p[b]. */
-struct SlotOuts {
-  int32_t* p[64];
-};
 hipError_t launch_ms_session_admit(const GView& g, const MsView& m, unsigned long long clear_bits, const MsRoots& r,
                                    const SlotOuts& outs, unsigned long long new_bits, int first_pull, int grid,
                                    hipStream_t s);
+/* Session, relabelled graphs: caller-order depths of the slots in `ended`
+   (roots r.r[b], outputs outs.p[b]) from their internal rows. */
+hipError_t launch_ms_session_finalize(const GView& g, const MsView& m, const MsRoots& r, const SlotOuts& outs,
+                                      unsigned long long ended, int grid, hipStream_t s);
 
 /* Kernel launchers (bfs_kernels.hip). */
 hipError_t launch_init(const GView& g, const WView& w, const int32_t* roots, int32_t nroots, int64_t root0,

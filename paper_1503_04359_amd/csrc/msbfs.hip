@@ -33,8 +33,9 @@ constexpr uint32_t kPullEntry = 0x80000000u;  /* split-list entry of a pull vert
 /* Depth d of vertex v for one slot b.  Outputs are slot-major, so lanes
    holding consecutive vertices write consecutive addresses. */
 __device__ __forceinline__ void ms_put(const GView& g, const MsView& m, int64_t v, int b, int32_t d) {
-  if (m.session) m.slot_out[b][g.new2old ? g.new2old[v] : v] = d - m.slot_start[b];
-  else if (m.internal) m.internal[(int64_t)b * g.n_nonisolated + v] = d;
+  if (m.session) d -= m.slot_start[b];
+  if (m.internal) m.internal[(int64_t)b * g.n_nonisolated + v] = d;
+  else if (m.session) m.slot_out[b][v] = d;
   else m.out[(int64_t)b * g.n + v] = d;
 }
 
@@ -592,7 +593,11 @@ __global__ void k_ms_session_seed(GView g, MsView m, MsRoots roots, SlotOuts out
     atomicOr(reinterpret_cast<unsigned long long*>(cur_in + v), bit);
     m.slot_out[b] = outs.p[b];
     m.slot_start[b] = L;
-    outs.p[b][rc] = 0;
+    if (m.internal) {
+      if ((int64_t)v < g.n_nonisolated) m.internal[(int64_t)b * g.n_nonisolated + v] = 0;
+    } else {
+      outs.p[b][rc] = 0;
+    }
     deg = g.off[v + 1] - g.off[v];
     slot_start_counts(c, b, deg, g.m);
   }
@@ -617,6 +622,40 @@ __global__ void k_ms_session_ctl(MsView m) {
   ctl_reset(c);
   c->done = 1;
   for (int b = 0; b < 64; ++b) slot_start_counts(c, b, 0, 0);
+}
+
+/* Session, relabelled graphs: each ended slot b gets
+   outs.p[b][x] = internal[b][old2new[x]] where it reached the vertex, else
+   -1 (its root: 0).  Ended slots keep their visit bits until reused. */
+__global__ void __launch_bounds__(kBlock) k_ms_session_finalize(GView g, MsView m, MsRoots roots, SlotOuts outs,
+                                                               unsigned long long ended) {
+  constexpr int kPer = 8;
+  const int64_t span = (int64_t)kBlock * kPer;
+  const int64_t nn = g.n_nonisolated;
+  for (int64_t x0 = (int64_t)blockIdx.x * span; x0 < g.n; x0 += (int64_t)gridDim.x * span) {
+    int32_t v[kPer];
+    uint64_t vis[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int64_t x = x0 + (int64_t)j * kBlock + threadIdx.x;
+      v[j] = x < g.n ? __builtin_nontemporal_load(g.old2new + x) : -1;
+      vis[j] = (v[j] >= 0 && (int64_t)v[j] < nn) ? m.visit[v[j]] : 0ull;
+    }
+    for (unsigned long long left = ended; left; left &= left - 1) {
+      const int b = __ffsll(left) - 1;
+      const int32_t rb = roots.r[b];
+      int32_t* ob = outs.p[b];
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int64_t x = x0 + (int64_t)j * kBlock + threadIdx.x;
+        if (x >= g.n) continue;
+        int32_t d;
+        if ((int64_t)v[j] < nn) d = ((vis[j] >> b) & 1ull) ? m.internal[(int64_t)b * nn + v[j]] : -1;
+        else d = (rb == (int32_t)x) ? 0 : -1;
+        __builtin_nontemporal_store(d, ob + x);
+      }
+    }
+  }
 }
 
 /* Relabelled graphs: out[b][x] = internal[b][old2new[x]] where slot b
@@ -680,6 +719,12 @@ hipError_t launch_ms_session_admit(const GView& g, const MsView& m, unsigned lon
                                    hipStream_t s) {
   if (clear_bits) hipLaunchKernelGGL(k_ms_session_clear, dim3(grid), dim3(kBlock), 0, s, g, m, clear_bits);
   hipLaunchKernelGGL(k_ms_session_seed, dim3(1), dim3(kWave), 0, s, g, m, r, outs, new_bits, first_pull);
+  return hipGetLastError();
+}
+
+hipError_t launch_ms_session_finalize(const GView& g, const MsView& m, const MsRoots& r, const SlotOuts& outs,
+                                      unsigned long long ended, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_ms_session_finalize, dim3(grid), dim3(kBlock), 0, s, g, m, r, outs, ended);
   return hipGetLastError();
 }
 

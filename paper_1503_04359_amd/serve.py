@@ -6,7 +6,10 @@ Two ways to serve the same open-loop trace of timed arrivals:
   the 64-slot batched traversal running; arrived queries join between level
   chunks as slots and device memory allow, and leave as soon as their own
   traversal ends, so queries that arrive while others run share the device
-  with them.
+  with them.  A query that finds its graph idle and nobody waiting behind
+  it runs as a plain single-source traversal instead (``solo_plain``): a
+  session level sweeps the whole graph, which only pays off when several
+  queries share it.
 * ``plain``: one worker serves the queries one at a time in arrival order,
   each a single-source traversal of its own.
 
@@ -132,12 +135,15 @@ class Server:
     """Serves a trace through an executor; see the module text."""
 
     def __init__(self, executor: Executor, memory_budget: int, slots: int = 64,
-                 clock: Callable[[], float] = time.perf_counter, poll_s: float = 2e-4):
+                 clock: Callable[[], float] = time.perf_counter, poll_s: float = 2e-4, solo_plain: bool = True):
         self.ex = executor
         self.budget = MemoryBudget(memory_budget)
         self.slots = slots
         self.clock = clock
         self.poll_s = poll_s
+        self.solo_plain = solo_plain
+        self.solo_runs = 0
+        self._count_lock = threading.Lock()
 
     # ---- batched -----------------------------------------------------------
     def _graph_worker(self, gid: int, queries: list[Query], t0: float, deadline: float,
@@ -152,6 +158,26 @@ class Server:
                 now = self.clock() - t0
                 if now > deadline:
                     break
+                if (self.solo_plain and not inflight and nxt < len(queries) and queries[nxt].t_arrival <= now
+                        and (nxt + 1 >= len(queries) or queries[nxt + 1].t_arrival > now)
+                        and self.budget.take(need)):
+                    q = queries[nxt]
+                    nxt += 1
+                    try:
+                        res = ex.run_plain(gid, q.root)
+                    except Exception as e:
+                        q.error = f"{type(e).__name__}: {e}"
+                        self.budget.give(need)
+                        continue
+                    q.t_done = self.clock() - t0
+                    with self._count_lock:
+                        self.solo_runs += 1
+                    if results is not None:
+                        results[q.qid] = res
+                    else:
+                        ex.release(res)
+                    self.budget.give(need)
+                    continue
                 while (nxt < len(queries) and queries[nxt].t_arrival <= now and len(inflight) < self.slots
                        and self.budget.take(need)):
                     q = queries[nxt]
@@ -292,7 +318,6 @@ class GpuExecutor:
         self.n_graphs = len(self.graphs)
         self.params = params
         self.streams = [torch.cuda.Stream() for _ in self.graphs]
-        self.plain_stream = torch.cuda.Stream()
 
     def output_bytes(self, gid: int) -> int:
         return 4 * self.graphs[gid].n
@@ -301,12 +326,15 @@ class GpuExecutor:
         return _GpuSession(self.graphs[gid], self.params, self.streams[gid])
 
     def run_plain(self, gid: int, root: int):
+        """On the graph's own stream: plain runs and the graph's session are
+        issued by the same worker, never at once."""
         import torch
         g = self.graphs[gid]
-        with torch.cuda.stream(self.plain_stream):
+        st = self.streams[gid]
+        with torch.cuda.stream(st):
             depth = torch.empty(g.n, dtype=torch.int32, device="cuda")
-        g.run(int(root), depth=depth, want_parent=False, params=self.params, stream=self.plain_stream)
-        self.plain_stream.synchronize()
+        g.run(int(root), depth=depth, want_parent=False, params=self.params, stream=st)
+        st.synchronize()
         return depth
 
     def release(self, result) -> None:

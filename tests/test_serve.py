@@ -49,12 +49,12 @@ def test_censored_percentile():
     assert serve._percentile_censored(np.array([]), 0, 50) is None
 
 
-@pytest.mark.parametrize("mode", ["batched", "plain"])
-def test_results_equal_single_source(mode):
+@pytest.mark.parametrize("mode,solo", [("batched", True), ("batched", False), ("plain", True)])
+def test_results_equal_single_source(mode, solo):
     gs = _graphs()
     ex = CpuExecutor([(g.offsets, g.indices) for g in gs])
     trace = serve.poisson_trace(400.0, 0.3, len(gs), _roots(gs), seed=1)
-    srv = serve.Server(ex, memory_budget=1 << 30)
+    srv = serve.Server(ex, memory_budget=1 << 30, solo_plain=solo)
     rep, res = srv.serve(trace, mode=mode, drain_s=30.0, keep_results=True)
     assert rep.completed == len(trace) and rep.unfinished == 0 and rep.failed == 0
     exp = _expected(gs, trace)
@@ -62,6 +62,8 @@ def test_results_equal_single_source(mode):
         assert np.array_equal(res[q.qid], exp[(q.gid, q.root)]), q
         assert q.t_done >= q.t_arrival
     assert rep.p50_ms is not None and rep.p99_ms >= rep.p50_ms
+    if mode == "batched":
+        assert (srv.solo_runs > 0) == solo
 
 
 def test_memory_budget_bounds_inflight_and_slots_refill():
@@ -100,7 +102,7 @@ def test_alone_equals_in_the_mix():
     gs = _graphs()
     ex = CpuExecutor([(g.offsets, g.indices) for g in gs])
     trace = serve.poisson_trace(2000.0, 0.2, len(gs), _roots(gs), seed=4)
-    srv = serve.Server(ex, memory_budget=1 << 30)
+    srv = serve.Server(ex, memory_budget=1 << 30, solo_plain=False)  # every query through a session
     _, mixed = srv.serve(trace, mode="batched", drain_s=30.0, keep_results=True)
     for q in trace[:15]:
         alone_trace = [serve.Query(0, q.gid, q.root, 0.0)]
