@@ -390,6 +390,8 @@ def main() -> int:
     ap.add_argument("--serve-drain", type=float, default=5.0)
     ap.add_argument("--serve-chunk", type=int, default=4)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--param", action="append", default=[], metavar="NAME=VALUE",
+                    help="override a dobfs_params field (e.g. alpha=14), repeatable")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=int, default=30)
@@ -466,7 +468,8 @@ def main() -> int:
     words_active = ((info["n_nonisolated"] if reindex else info["n"]) + 63) // 64
     depth = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
-    params = dobfs.make_params(args.policy, flags=dobfs.RUN_TIME_KERNELS)
+    overrides = {k: int(v) for k, v in (kv.split("=", 1) for kv in args.param)}
+    params = dobfs.make_params(args.policy, flags=dobfs.RUN_TIME_KERNELS, **overrides)
 
     def one_step(record):
         for r in roots:
@@ -536,7 +539,8 @@ def main() -> int:
                                   f"A/B/C 0.57/0.19/0.19 seed {args.seed}, {args.roots} roots, "
                                   f"single-source DOBFS, policy {args.policy}, degree relabel {args.reindex}",
                       "scale": args.scale, "edgefactor": args.edgefactor, "n": n, "m": m,
-                      "roots": args.roots, "policy": args.policy, "reindex": reindex},
+                      "roots": args.roots, "policy": args.policy, "reindex": reindex,
+                      "params": overrides},
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     dg.free()

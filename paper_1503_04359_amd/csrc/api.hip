@@ -99,6 +99,7 @@ struct dobfs_graph_s {
   int64_t* off = nullptr;
   int32_t* idx = nullptr;
   uint64_t* iso = nullptr;
+  int32_t* first = nullptr;    /* first neighbour of each vertex, -1 if none */
   int32_t* new2old = nullptr;  /* relabelled graphs only */
   int32_t* old2new = nullptr;
   int64_t* seg_lo = nullptr;
@@ -115,6 +116,7 @@ struct dobfs_graph_s {
     g.off = off;
     g.idx = idx;
     g.iso = iso;
+    g.first = first;
     g.old2new = old2new;
     g.new2old = new2old;
     g.seg_lo = seg_lo;
@@ -397,6 +399,7 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
         dfree(g->idx);
       }
       dfree(g->iso);
+      dfree(g->first);
       dfree(g->new2old);
       dfree(g->old2new);
       dfree(g->seg_lo);
@@ -473,8 +476,11 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
     drop_tmp();
     if (st != DOBFS_OK) return cleanup(fail(st, err.c_str()));
   }
+  if ((e = dalloc(&g->first, n)) != hipSuccess)
+    return cleanup(fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "first-neighbour column", e));
   if ((e = hipMemsetAsync(counters, 0, 4 * sizeof(int64_t), s)) != hipSuccess ||
-      (e = launch_graph_scan(g->off, n, g->iso, counters, g->grid, s)) != hipSuccess)
+      (e = launch_graph_scan(g->off, n, g->iso, counters, g->grid, s)) != hipSuccess ||
+      (e = launch_first_column(g->off, g->idx, n, g->first, g->grid, s)) != hipSuccess)
     return cleanup(fail(DOBFS_EDEVICE, "degree scan", e));
   int64_t ch[4] = {0, 0, 0, 0};
   if ((e = hipMemcpyAsync(ch, counters, sizeof(ch), hipMemcpyDeviceToHost, s)) != hipSuccess ||
@@ -504,6 +510,7 @@ int dobfs_graph_free(dobfs_graph_t g) {
     dfree(g->idx);
   }
   dfree(g->iso);
+  dfree(g->first);
   dfree(g->new2old);
   dfree(g->old2new);
   dfree(g->seg_lo);
@@ -519,7 +526,7 @@ int dobfs_graph_info(dobfs_graph_t g, dobfs_graph_info_t* info) {
   info->n_nonisolated = g->n_nonisolated;
   info->max_degree = g->max_degree;
   info->device_bytes = (g->owns_csr ? (int64_t)sizeof(int64_t) * (g->n + 1) + (int64_t)sizeof(int32_t) * g->m : 0) +
-                       (int64_t)sizeof(uint64_t) * g->words + (g->new2old ? 8 * g->n : 0);
+                       (int64_t)sizeof(uint64_t) * g->words + 4 * g->n + (g->new2old ? 8 * g->n : 0);
   info->flags = g->flags;
   return DOBFS_OK;
 }

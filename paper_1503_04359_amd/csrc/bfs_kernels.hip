@@ -283,9 +283,10 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
     a.scanned += unv ? 1 : 0;
     bool found = false;
     int32_t par = -1;
-    /* round 0: own first neighbour */
+    /* round 0: own first neighbour, from the first-neighbour column (one
+       coalesced read instead of a line per row) */
     if (pos < end) {
-      const int32_t u = g.idx[pos];
+      const int32_t u = g.first[v];
       a.checked += 1;
       if (test_bit(f_cur, u)) {
         found = true;
@@ -570,11 +571,12 @@ __global__ void __launch_bounds__(kBlock) k_finalize(GView g, WView w, int32_t r
       rec[j] = in ? (uint64_t)w.packed[v[j]] : 0ull;
     }
     int32_t d[kFinUnroll], p[kFinUnroll];
+    const bool want_parent = w.parent != nullptr; /* parents are mapped only when asked for */
 #pragma unroll
     for (int j = 0; j < kFinUnroll; ++j) {
       const bool hit = (word[j] >> (v[j] & 63)) & 1ull;
       d[j] = hit ? (int32_t)(uint32_t)(rec[j] & 0xFFFFFFFFull) : -1;
-      p[j] = hit ? g.new2old[(int32_t)(uint32_t)(rec[j] >> 32)] : -1;
+      p[j] = (hit && want_parent) ? g.new2old[(int32_t)(uint32_t)(rec[j] >> 32)] : -1;
     }
 #pragma unroll
     for (int j = 0; j < kFinUnroll; ++j) {

@@ -98,6 +98,16 @@ __global__ void __launch_bounds__(kBlock) k_validate_symmetry(const int64_t* off
   }
 }
 
+/* first[v] = the first entry of v's row, -1 for degree 0. */
+__global__ void __launch_bounds__(kBlock) k_first_column(const int64_t* off, const int32_t* idx, int64_t n,
+                                                       int32_t* first) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += nth) {
+    const int64_t b = off[v];
+    first[v] = b < off[v + 1] ? idx[b] : -1;
+  }
+}
+
 __global__ void k_shift_i64(int64_t* dst, const int64_t* src, int64_t count, int64_t add) {
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += nth) dst[i] = src[i] + add;
@@ -148,6 +158,12 @@ hipError_t launch_pack_copy(const int64_t* off, const int32_t* idx, int64_t n, i
     if (e == hipSuccess) e = e2;
   }
   return e;
+}
+
+hipError_t launch_first_column(const int64_t* off, const int32_t* idx, int64_t n, int32_t* first, int grid,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_first_column, dim3(grid), dim3(kBlock), 0, s, off, idx, n, first);
+  return hipGetLastError();
 }
 
 hipError_t launch_graph_scan(const int64_t* off, int64_t n, uint64_t* iso, int64_t* counters, int grid,

@@ -284,8 +284,8 @@ __device__ void ms_pull(const GView& g, const MsView& m, const uint64_t* cur_in,
     const int64_t full_end = end;
     if (longrow) end = pos + kMsPullProbe;
     uint64_t acc = 0ull;
-    if (pos < end) { /* round 0: own first neighbour */
-      acc = cur_in[g.idx[pos]];
+    if (pos < end) { /* round 0: own first neighbour, from the first-neighbour column */
+      acc = cur_in[g.first[v]];
       a.checked += 1;
       ++pos;
     }

@@ -259,3 +259,4 @@ def test_cost_policy(dobfs):
         _parity(dobfs, g, roots, params=dobfs.make_params("cost", kappa_x1000=kap), label=f"kron14/cost{kap}")
         _parity(dobfs, g, roots, params=dobfs.make_params("cost", kappa_x1000=kap), label=f"kron14/cost{kap}/reindex",
                 reindex=True)
+
