@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -100,6 +101,10 @@ struct dobfs_graph_s {
   int32_t* idx = nullptr;
   uint64_t* iso = nullptr;
   int32_t* first = nullptr;    /* first neighbour of each vertex, -1 if none */
+  int32_t* first_caller = nullptr; /* relabelled graphs: its caller ID, built by the
+                                       first run (the caller may free the source
+                                       CSR after upload), skipped if memory is short */
+  std::atomic<bool> first_caller_tried{false};
   int32_t* new2old = nullptr;  /* relabelled graphs only */
   int32_t* old2new = nullptr;
   int64_t* seg_lo = nullptr;
@@ -117,6 +122,7 @@ struct dobfs_graph_s {
     g.idx = idx;
     g.iso = iso;
     g.first = first;
+    g.first_caller = first_caller;
     g.old2new = old2new;
     g.new2old = new2old;
     g.seg_lo = seg_lo;
@@ -400,6 +406,7 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
       }
       dfree(g->iso);
       dfree(g->first);
+      dfree(g->first_caller);
       dfree(g->new2old);
       dfree(g->old2new);
       dfree(g->seg_lo);
@@ -482,6 +489,7 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
       (e = launch_graph_scan(g->off, n, g->iso, counters, g->grid, s)) != hipSuccess ||
       (e = launch_first_column(g->off, g->idx, n, g->first, g->grid, s)) != hipSuccess)
     return cleanup(fail(DOBFS_EDEVICE, "degree scan", e));
+
   int64_t ch[4] = {0, 0, 0, 0};
   if ((e = hipMemcpyAsync(ch, counters, sizeof(ch), hipMemcpyDeviceToHost, s)) != hipSuccess ||
       (e = hipStreamSynchronize(s)) != hipSuccess)
@@ -511,6 +519,7 @@ int dobfs_graph_free(dobfs_graph_t g) {
   }
   dfree(g->iso);
   dfree(g->first);
+  dfree(g->first_caller);
   dfree(g->new2old);
   dfree(g->old2new);
   dfree(g->seg_lo);
@@ -526,7 +535,8 @@ int dobfs_graph_info(dobfs_graph_t g, dobfs_graph_info_t* info) {
   info->n_nonisolated = g->n_nonisolated;
   info->max_degree = g->max_degree;
   info->device_bytes = (g->owns_csr ? (int64_t)sizeof(int64_t) * (g->n + 1) + (int64_t)sizeof(int32_t) * g->m : 0) +
-                       (int64_t)sizeof(uint64_t) * g->words + 4 * g->n + (g->new2old ? 8 * g->n : 0);
+                       (int64_t)sizeof(uint64_t) * g->words + 4 * g->n + (g->new2old ? 8 * g->n : 0) +
+                       (g->first_caller ? 4 * g->n : 0);
   info->flags = g->flags;
   return DOBFS_OK;
 }
@@ -550,6 +560,21 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
   if (st != DOBFS_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Workspace* w = nullptr;
+  if (g->new2old && !g->first_caller_tried) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (!g->first_caller_tried) {
+      g->first_caller_tried = true;
+      hipError_t e2 = dalloc(&g->first_caller, g->n);
+      if (e2 == hipSuccess) {
+        e2 = launch_first_caller(g->first, g->new2old, g->n, g->first_caller, g->grid, s);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+        if (e2 != hipSuccess) return fail(DOBFS_EDEVICE, "first-neighbour caller column", e2);
+      } else {
+        g->first_caller = nullptr; /* optional: parents are then all mapped by the finalize kernel */
+        (void)hipGetLastError();
+      }
+    }
+  }
   if ((st = acquire_workspace(g, &w)) != DOBFS_OK) return st;
   struct Guard {
     dobfs_graph_s* g;

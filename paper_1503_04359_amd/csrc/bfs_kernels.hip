@@ -129,21 +129,29 @@ __device__ void decide(const GView& g, const WView& w, const KParams& kp) {
 
 /* Writes the labels of a newly reached vertex: the caller's depth/parent
    arrays, or (relabelled graphs) one packed (parent << 32 | depth) word in
-   internal labels that the finalize kernel maps back. */
-__device__ __forceinline__ void store_labels(const WView& w, int32_t v, int32_t d, int32_t p) {
+   internal labels that the finalize kernel maps back.  When the parent's
+   caller ID pc is already at hand (pc >= 0) it is stored instead, flagged
+   by kCallerParent in the depth field, and the finalize kernel uses it as
+   is. */
+constexpr uint32_t kCallerParent = 0x80000000u;
+
+__device__ __forceinline__ void store_labels(const WView& w, int32_t v, int32_t d, int32_t p, int32_t pc = -1) {
   if (w.packed) {
-    w.packed[v] = (int64_t)(((uint64_t)(uint32_t)p << 32) | (uint64_t)(uint32_t)d);
+    const uint64_t pf = (uint64_t)(uint32_t)(pc >= 0 ? pc : p);
+    const uint64_t df = (uint64_t)((uint32_t)d | (pc >= 0 ? kCallerParent : 0u));
+    w.packed[v] = (int64_t)((pf << 32) | df);
   } else {
     w.depth[v] = d;
     w.parent[v] = p;
   }
 }
 
-/* Bookkeeping of a vertex v claimed from u at level L: labels, next-frontier
-   bit and the degree sum that feeds the switching rule. */
+/* Bookkeeping of a vertex v claimed from u (caller ID uc, or -1) at level L:
+   labels, next-frontier bit and the degree sum that feeds the switching
+   rule. */
 __device__ __forceinline__ void claimed(const GView& g, const WView& w, uint64_t* f_nxt, int32_t v, int32_t u,
-                                        int32_t L, Acc& a) {
-  store_labels(w, v, L + 1, u);
+                                        int32_t uc, int32_t L, Acc& a) {
+  store_labels(w, v, L + 1, u, uc);
   atomicOr(reinterpret_cast<unsigned long long*>(f_nxt + (v >> 6)), 1ull << (v & 63));
   a.found += 1;
   a.found_deg += g.off[v + 1] - g.off[v];
@@ -162,12 +170,13 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
   for (int64_t base = wave * kWave; base < nf; base += nwaves * kWave) {
     const int64_t i = base + lane;
     const bool valid = i < nf;
-    int32_t u = 0;
+    int32_t u = 0, uc = -1;
     int64_t beg = 0, deg = 0;
     if (valid) {
       u = q_cur[i];
       beg = g.off[u];
       deg = g.off[u + 1] - beg;
+      if (g.new2old) uc = g.new2old[u]; /* one lookup per frontier vertex, not per claim */
     }
     a.checked += deg;
     const bool huge = valid && deg > huge_cut;
@@ -177,7 +186,7 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
     const int64_t sdeg = (valid && !huge && !med) ? deg : 0;
     for (int64_t j = 0; j < sdeg; ++j) {
       const int32_t v = g.idx[beg + j];
-      if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, u, L, a);
+      if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, u, uc, L, a);
     }
 
     /* wavefront per vertex */
@@ -185,12 +194,12 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
     while (mm) {
       const int src = __ffsll((unsigned long long)mm) - 1;
       mm &= mm - 1;
-      const int32_t uu = __shfl(u, src);
+      const int32_t uu = __shfl(u, src), uuc = __shfl(uc, src);
       const int64_t bb = __shfl(beg, src);
       const int64_t dd = __shfl(deg, src);
       for (int64_t k = lane; k < dd; k += kWave) {
         const int32_t v = g.idx[bb + k];
-        if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, uu, L, a);
+        if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, uu, uuc, L, a);
       }
     }
 
@@ -281,7 +290,7 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
     }
     const int64_t deg = end - pos;
     a.scanned += unv ? 1 : 0;
-    bool found = false;
+    bool found = false, hit0 = false;
     int32_t par = -1;
     /* round 0: own first neighbour, from the first-neighbour column (one
        coalesced read instead of a line per row) */
@@ -289,7 +298,7 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
       const int32_t u = g.first[v];
       a.checked += 1;
       if (test_bit(f_cur, u)) {
-        found = true;
+        found = hit0 = true;
         par = u;
       }
       ++pos;
@@ -319,7 +328,8 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
     }
     const uint64_t fm = __ballot(found);
     if (found) {
-      store_labels(w, v, L + 1, par);
+      /* a round-0 parent's caller ID is in the matching column */
+      store_labels(w, v, L + 1, par, (hit0 && g.first_caller) ? g.first_caller[v] : -1);
       a.found_deg += deg;
       a.found += 1;
     }
@@ -401,12 +411,13 @@ __global__ void __launch_bounds__(kBlock) k_aux(GView g, WView w, KParams kp) {
     for (int64_t ch = c0; ch < c1; ++ch) {
       while (lo + 1 < nent && (int64_t)w.huge_base[lo + 1] <= ch) ++lo;
       const int32_t u = w.huge_u[lo];
+      const int32_t uc = g.new2old ? g.new2old[u] : -1;
       const int64_t rb = g.off[u], re = g.off[u + 1];
       const int64_t beg = rb + (ch - (int64_t)w.huge_base[lo]) * kHugeChunk;
       const int64_t end = min(re, beg + (int64_t)kHugeChunk);
       for (int64_t k = beg + lane; k < end; k += kWave) {
         const int32_t v = g.idx[k];
-        if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, u, L, a);
+        if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, u, uc, L, a);
       }
     }
     if (finish_block(c, a)) {
@@ -575,8 +586,9 @@ __global__ void __launch_bounds__(kBlock) k_finalize(GView g, WView w, int32_t r
 #pragma unroll
     for (int j = 0; j < kFinUnroll; ++j) {
       const bool hit = (word[j] >> (v[j] & 63)) & 1ull;
-      d[j] = hit ? (int32_t)(uint32_t)(rec[j] & 0xFFFFFFFFull) : -1;
-      p[j] = (hit && want_parent) ? g.new2old[(int32_t)(uint32_t)(rec[j] >> 32)] : -1;
+      const uint32_t df = (uint32_t)(rec[j] & 0xFFFFFFFFull), pf = (uint32_t)(rec[j] >> 32);
+      d[j] = hit ? (int32_t)(df & ~kCallerParent) : -1;
+      p[j] = (hit && want_parent) ? ((df & kCallerParent) ? (int32_t)pf : g.new2old[(int32_t)pf]) : -1;
     }
 #pragma unroll
     for (int j = 0; j < kFinUnroll; ++j) {

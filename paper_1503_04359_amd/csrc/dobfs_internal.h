@@ -123,6 +123,7 @@ struct GView {
   const uint64_t* iso;
   const int32_t* first;    /* first neighbour of each vertex (-1: degree 0): the
                               bottom-up round 0 reads it as one coalesced column */
+  const int32_t* first_caller; /* relabelled graphs: caller ID of first[v]   */
   const int32_t* old2new;  /* relabelled graphs: caller ID -> internal ID  */
   const int32_t* new2old;  /* relabelled graphs: internal ID -> caller ID  */
   const int64_t* seg_lo;   /* relabelled graphs: internal start of each degree
@@ -213,6 +214,8 @@ int build_reindexed(const int64_t* off, const int32_t* idx, int64_t n, int64_t m
                     int64_t** seg_lo, int32_t* nseg, std::string* err);
 
 /* Graph preparation launchers (graph_kernels.hip). */
+hipError_t launch_first_caller(const int32_t* first, const int32_t* new2old, int64_t n, int32_t* out, int grid,
+                               hipStream_t s);
 hipError_t launch_first_column(const int64_t* off, const int32_t* idx, int64_t n, int32_t* first, int grid,
                                hipStream_t s);
 hipError_t launch_graph_scan(const int64_t* off, int64_t n, uint64_t* iso, int64_t* counters,

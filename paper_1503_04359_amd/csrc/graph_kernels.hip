@@ -108,6 +108,16 @@ __global__ void __launch_bounds__(kBlock) k_first_column(const int64_t* off, con
   }
 }
 
+/* out[v] = caller ID of first[v] (relabelled graphs). */
+__global__ void __launch_bounds__(kBlock) k_first_caller(const int32_t* first, const int32_t* new2old, int64_t n,
+                                                       int32_t* out) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += nth) {
+    const int32_t u = first[v];
+    out[v] = u >= 0 ? new2old[u] : -1;
+  }
+}
+
 __global__ void k_shift_i64(int64_t* dst, const int64_t* src, int64_t count, int64_t add) {
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += nth) dst[i] = src[i] + add;
@@ -158,6 +168,12 @@ hipError_t launch_pack_copy(const int64_t* off, const int32_t* idx, int64_t n, i
     if (e == hipSuccess) e = e2;
   }
   return e;
+}
+
+hipError_t launch_first_caller(const int32_t* first, const int32_t* new2old, int64_t n, int32_t* out, int grid,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_first_caller, dim3(grid), dim3(kBlock), 0, s, first, new2old, n, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_first_column(const int64_t* off, const int32_t* idx, int64_t n, int32_t* first, int grid,
