@@ -37,6 +37,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GTEPS (harmonic mean over roots) at scale 30; served queries/s + p99 vs plain"
 HBM_PEAK_GBS = 8000.0
+# the level step: both direction kernels are launched for every level and the
+# one not matching the level's direction returns at once; a "launch" below is
+# that pair
+LEVEL_KERNEL = "k_level_td+k_level_bu"
 
 
 def log(*a):
@@ -346,7 +350,9 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, probe_bytes: int, key:
     import csv
 
     def load(path, counter):
-        probe, level = [], []
+        """Copy-probe reading, summed level-kernel readings, level slots (one
+        k_level_bu dispatch per slot)."""
+        probe, level, slots = [], 0.0, 0
         with open(path) as f:
             for r in csv.DictReader(f):
                 if r["Counter_Name"] != counter:
@@ -354,19 +360,20 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, probe_bytes: int, key:
                 name, val = r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0
                 if "CUDAFunctorOnSelf_add" in name:
                     probe.append(val)
-                elif "k_level(" in name:
-                    level.append(val)
-        if not probe or not level:
+                elif "k_level_td(" in name or "k_level_bu(" in name:
+                    level += val
+                    slots += "k_level_bu(" in name
+        if not probe or not slots:
             raise ValueError(f"{path}: no copy-probe or level-kernel dispatches for {counter}")
-        return probe[0], level
+        return probe[0], level, slots
 
-    pf, lf = load(fetch_csv, "FETCH_SIZE")
-    pw, lw = load(write_csv, "WRITE_SIZE")
+    pf, lf, nf = load(fetch_csv, "FETCH_SIZE")
+    pw, lw, nw = load(write_csv, "WRITE_SIZE")
     kf, kw = probe_bytes / pf, probe_bytes / pw
-    per_launch = (sum(lf) * kf + sum(lw) * kw) / len(lf)
-    ent = {"kernel": "k_level", "source_sha256": kernel_source_digest(), "bytes_per_launch": round(per_launch),
-           "fetch_factor": round(kf, 4), "write_factor": round(kw, 4), "launches": len(lf),
-           "fetch_bytes_per_launch": round(sum(lf) * kf / len(lf)), "write_bytes_per_launch": round(sum(lw) * kw / len(lw))}
+    per_launch = lf * kf / nf + lw * kw / nw
+    ent = {"kernel": LEVEL_KERNEL, "source_sha256": kernel_source_digest(), "bytes_per_launch": round(per_launch),
+           "fetch_factor": round(kf, 4), "write_factor": round(kw, 4), "launches": nf,
+           "fetch_bytes_per_launch": round(lf * kf / nf), "write_bytes_per_launch": round(lw * kw / nw)}
     data = {}
     if os.path.exists(out_path):
         with open(out_path) as f:
@@ -517,11 +524,11 @@ def main() -> int:
                 tr = json.load(f)
             key = f"kron-s{args.scale}-ef{args.edgefactor}-seed{args.seed}/{args.policy}/reindex-{args.reindex}"
             ent = tr.get(key, {})
-            if ent.get("kernel") == "k_level" and ent.get("source_sha256") == kernel_source_digest():
+            if ent.get("kernel") == LEVEL_KERNEL and ent.get("source_sha256") == kernel_source_digest():
                 traffic = ent["bytes_per_launch"]
         except (OSError, ValueError):
             traffic = None
-    roofline = {"bound": "hbm", "kernel": "k_level", "source_sha256": kernel_source_digest()[:16], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    roofline = {"bound": "hbm", "kernel": LEVEL_KERNEL, "source_sha256": kernel_source_digest()[:16], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": round(per_launch), "avg_launch_ms": round(avg_ms, 5),
                 "launches": tot_launch}

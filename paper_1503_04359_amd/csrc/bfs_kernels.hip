@@ -230,7 +230,7 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
    it is [max(excl,c0), min(incl,c0+64)); H marks the entries that hit the
    frontier.  Records the first hit of the slice as the lane's parent. */
 __device__ __forceinline__ void resolve_chunk(uint64_t H, int c0, int excl, int incl, int take, int32_t u,
-                                              bool& found, int32_t& par, Acc& a) {
+                                              bool& found, int32_t& par, int32_t& checked) {
   const int lane = lane_id();
   const int sa = max(excl, c0) - c0, sb = min(incl, c0 + kWave) - c0;
   int src = lane;
@@ -241,9 +241,9 @@ __device__ __forceinline__ void resolve_chunk(uint64_t H, int c0, int excl, int 
     if (h) {
       src = __ffsll((unsigned long long)h) - 1;
       got = true;
-      a.checked += src - sa + 1;
+      checked += src - sa + 1;
     } else {
-      a.checked += sb - sa;
+      checked += sb - sa;
     }
   }
   const int32_t pu = __shfl(u, src);
@@ -272,6 +272,9 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const int max_quota = kp.bu_heavy_cut < kWave ? kWave : kp.bu_heavy_cut;
   const int64_t W = g.words_active;
+  /* per-lane counts in 32 bits (a lane sees far fewer than 2^31 entries per
+     level); they join the 64-bit accumulators once at the end */
+  int32_t n_scanned = 0, n_checked = 0, n_found = 0;
 
   uint64_t vis_next = wave < W ? w.vis[wave] : ~0ull;
   for (int64_t wd = wave; wd < W; wd += nwaves) {
@@ -289,14 +292,14 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
       end = g.off[v + 1];
     }
     const int64_t deg = end - pos;
-    a.scanned += unv ? 1 : 0;
+    n_scanned += unv ? 1 : 0;
     bool found = false, hit0 = false;
     int32_t par = -1;
     /* round 0: own first neighbour, from the first-neighbour column (one
        coalesced read instead of a line per row) */
     if (pos < end) {
       const int32_t u = g.first[v];
-      a.checked += 1;
+      n_checked += 1;
       if (test_bit(f_cur, u)) {
         found = hit0 = true;
         par = u;
@@ -320,8 +323,8 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
         const bool h1 = p1 < total && test_bit(f_cur, u1);
         const bool h2 = p2 < total && test_bit(f_cur, u2);
         const uint64_t H1 = __ballot(h1), H2 = __ballot(h2);
-        resolve_chunk(H1, c0, excl, incl, take, u1, found, par, a);
-        resolve_chunk(H2, c0 + kWave, excl, incl, take, u2, found, par, a);
+        resolve_chunk(H1, c0, excl, incl, take, u1, found, par, n_checked);
+        resolve_chunk(H2, c0 + kWave, excl, incl, take, u2, found, par, n_checked);
       }
       pos += take;
       if (quota < max_quota) quota <<= 1;
@@ -331,30 +334,43 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
       /* a round-0 parent's caller ID is in the matching column */
       store_labels(w, v, L + 1, par, (hit0 && g.first_caller) ? g.first_caller[v] : -1);
       a.found_deg += deg;
-      a.found += 1;
+      n_found += 1;
     }
     if (lane == 0) {
       f_nxt[wd] = fm;
       if (fm) w.vis[wd] = vis | fm;
     }
   }
+  a.scanned += n_scanned;
+  a.checked += n_checked;
+  a.found += n_found;
 }
 
-__global__ void __launch_bounds__(kBlock, 8) k_level(GView g, WView w, KParams kp) {
+/* The level kernels: top-down and bottom-up are separate kernels, both
+   launched for every level, so that each gets its own register allocation;
+   the one whose direction is not the level's returns at once. */
+__device__ __forceinline__ void level_body(const GView& g, const WView& w, const KParams& kp, int32_t want_dir) {
   Ctl* c = w.ctl;
-  if (c->done || c->aux != kAuxNone) return;
+  if (c->done || c->aux != kAuxNone || c->dir != want_dir) return;
   const int32_t L = c->level;
-  const int32_t dir = c->dir;
   Acc a = {0, 0, 0, 0};
-  if (dir == kDirTD) top_down(g, w, kp, L, a);
+  if (want_dir == kDirTD) top_down(g, w, kp, L, a);
   else bottom_up(g, w, kp, L, a);
   if (finish_block(c, a)) {
-    if (dir == kDirTD && ld_agent(&c->huge_pack) != 0ull) {
+    if (want_dir == kDirTD && ld_agent(&c->huge_pack) != 0ull) {
       c->aux = kAuxHuge;
     } else {
       decide(g, w, kp);
     }
   }
+}
+
+__global__ void __launch_bounds__(kBlock, 8) k_level_td(GView g, WView w, KParams kp) {
+  level_body(g, w, kp, kDirTD);
+}
+
+__global__ void __launch_bounds__(kBlock, 8) k_level_bu(GView g, WView w, KParams kp) {
+  level_body(g, w, kp, kDirBU);
 }
 
 /* Exclusive prefix sum over the workgroup; *total gets the sum. */
@@ -612,7 +628,7 @@ hipError_t level_grid(int* grid) {
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_level), kBlock, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_level_bu), kBlock, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   *grid = cus * per_cu;
@@ -632,7 +648,10 @@ hipError_t launch_fix_roots(const WView& w, const int32_t* roots, int32_t nroots
 }
 
 hipError_t launch_level(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_level, dim3(grid), dim3(kBlock), 0, s, g, w, kp);
+  /* a top-down level that ends by deciding bottom-up lets the next level
+     run in the same slot */
+  hipLaunchKernelGGL(k_level_td, dim3(grid), dim3(kBlock), 0, s, g, w, kp);
+  hipLaunchKernelGGL(k_level_bu, dim3(grid), dim3(kBlock), 0, s, g, w, kp);
   return hipGetLastError();
 }
 
