@@ -17,6 +17,10 @@ Other modes (--mode), each printing one JSON line of its own:
   pack   2,000 Kronecker graphs of scales drawn uniformly from 10..18, one
          root each, packed and traversed in one pass, against 2,000 separate
          single-source runs.
+  chunglu  Chung-Lu power-law graph standing in for a real-world graph:
+         100M core vertices, exponent 2.2, mean degree 20, max 10^6, plus 50
+         path tails of 200 vertices (hundreds of levels, several direction
+         switches), built on the host; 16 roots, harmonic-mean GTEPS.
   serve  8 resident Kronecker graphs (scales 18, 20, 22, 24, 24, 25, 26, 26),
          Poisson arrivals of (graph, root) queries at several rates, served
          with continuous batching and, as the baseline, one plain run at a
@@ -243,6 +247,62 @@ def bench_pack(args) -> dict:
             "speedup_vs_sequential": round(seq_ms / pack_ms, 3)}
 
 
+def bench_chunglu(args) -> dict:
+    """Single-source DOBFS on the Chung-Lu stand-in for a real-world graph."""
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import paper_1503_04359_amd as dobfs
+    n_core, seed = args.cl_core, 3
+    t0 = time.time()
+    g = gg.chung_lu(n_core, gamma=2.2, avg_deg=20.0, max_deg=1e6, n_tails=50, tail_len=200, seed=seed)
+    log(f"[chunglu] host-built in {time.time() - t0:.1f}s (n={g.n}, m={g.m}, max degree {int(g.degrees().max())})")
+    roots = gg.sample_roots(g, args.roots, seed=seed + 1_000_000)
+    reindex = args.reindex == "on"
+    t0 = time.time()
+    dg = dobfs.Graph.upload(g.offsets, g.indices, reindex=reindex)
+    torch.cuda.synchronize()
+    log(f"[chunglu] resident in {time.time() - t0:.1f}s")
+    n, m = g.n, g.m
+    del g
+    stream = torch.cuda.current_stream()
+    depth = torch.empty(n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(n, dtype=torch.int32, device="cuda")
+    params = dobfs.make_params(args.policy)
+    for r in roots:  # warm-up
+        dg.run(int(r), depth, parent, params=params, stream=stream)
+    torch.cuda.synchronize()
+    teps, times, lines = [], [], []
+    for _ in range(args.steps):
+        for r in roots:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            _, _, st = dg.run(int(r), depth, parent, params=params, stats=True, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            times.append(ms)
+            teps.append(st.m_c / (ms * 1e-3))
+            dirs = "".join("TB"[rec["dir"]] for rec in st.log)
+            switches = sum(1 for a, b in zip(dirs, dirs[1:]) if a != b)
+            lines.append((int(r), st.levels, switches, ms))
+    gteps = harmonic_mean(teps) / 1e9
+    for r, lv, sw, ms in lines[:len(roots)]:
+        log(f"[chunglu] root {r}: {lv} levels, {sw} direction switches, {ms:.2f} ms")
+    log(f"[chunglu] {gteps:.1f} GTEPS harmonic mean")
+    dg.free()
+    return {"metric": "GTEPS (harmonic mean over roots), Chung-Lu power-law graph with path tails",
+            "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": round(sum(times) / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": f"Chung-Lu {n_core} core vertices, exponent 2.2, mean degree 20, max 1e6, "
+                                   f"50 tails x 200 (seed {seed}), {args.roots} roots (seed {seed + 1_000_000}), "
+                                   f"policy {args.policy}, degree relabel {args.reindex}", "n": n, "m": m,
+                       "levels": [lv for _, lv, _, _ in lines[:len(roots)]],
+                       "direction_switches": [sw for _, _, sw, _ in lines[:len(roots)]]}}
+
+
 def _traversed_edges(dobfs, graphs, queries):
     """Undirected edges each query's traversal covers: one run per graph
     marks the component of its first root; other roots are run alone."""
@@ -390,7 +450,8 @@ def main() -> int:
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter CSVs of this bench "
                          "(run with --copy-probe) and exit")
-    ap.add_argument("--mode", choices=("single", "batch", "pack", "serve"), default="single")
+    ap.add_argument("--mode", choices=("single", "batch", "pack", "serve", "chunglu"), default="single")
+    ap.add_argument("--cl-core", type=int, default=100_000_000, help="chunglu mode: core vertices")
     ap.add_argument("--pack-graphs", type=int, default=2000)
     ap.add_argument("--serve-rates", default="500,2000,8000")
     ap.add_argument("--serve-duration", type=float, default=10.0)
@@ -441,7 +502,7 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     if args.mode != "single":
-        fn = {"batch": bench_batch, "pack": bench_pack, "serve": bench_serve}[args.mode]
+        fn = {"batch": bench_batch, "pack": bench_pack, "serve": bench_serve, "chunglu": bench_chunglu}[args.mode]
         print(json.dumps(fn(args)), flush=True)
         return 0
     stream = torch.cuda.current_stream()

@@ -50,6 +50,8 @@ struct Workspace {
   uint64_t* fr0 = nullptr;
   uint64_t* fr1 = nullptr;
   int32_t* q0 = nullptr;
+  int32_t* qd0 = nullptr;
+  int32_t* qd1 = nullptr;
   int32_t* huge_u = nullptr;
   uint32_t* huge_base = nullptr;
   int32_t* parent_scratch = nullptr;
@@ -74,7 +76,7 @@ struct Workspace {
 
   void release() {
     dfree(ms_visit); dfree(ms_cur0); dfree(ms_cur1); dfree(ms_nxt); dfree(ms_internal); dfree(roots_dev);
-    dfree(vis); dfree(fr0); dfree(fr1); dfree(q0);
+    dfree(vis); dfree(fr0); dfree(fr1); dfree(q0); dfree(qd0); dfree(qd1);
     dfree(huge_u); dfree(huge_base); dfree(parent_scratch); dfree(packed); dfree(ctl); dfree(log);
     if (done_host) (void)hipHostFree(done_host);
     for (auto& e : ev) if (e) (void)hipEventDestroy(e);
@@ -169,7 +171,9 @@ int alloc_workspace(dobfs_graph_s* g, Workspace* w) {
   const int64_t W = g->words;
   hipError_t e;
   if ((e = dalloc(&w->vis, W)) != hipSuccess || (e = dalloc(&w->fr0, W)) != hipSuccess ||
-      (e = dalloc(&w->fr1, W)) != hipSuccess || (e = dalloc(&w->q0, g->n)) != hipSuccess || (e = dalloc(&w->huge_u, g->n_huge)) != hipSuccess ||
+      (e = dalloc(&w->fr1, W)) != hipSuccess || (e = dalloc(&w->q0, g->n)) != hipSuccess ||
+      (e = dalloc(&w->qd0, kDirectCap)) != hipSuccess || (e = dalloc(&w->qd1, kDirectCap)) != hipSuccess ||
+      (e = dalloc(&w->huge_u, g->n_huge)) != hipSuccess ||
       (e = dalloc(&w->huge_base, g->n_huge)) != hipSuccess || (e = dalloc(&w->ctl, 1)) != hipSuccess ||
       (e = dalloc(&w->log, kLogCap)) != hipSuccess ||
       (g->new2old && (e = dalloc(&w->packed, g->n)) != hipSuccess)) {
@@ -594,6 +598,8 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
   wv.fr0 = w->fr0;
   wv.fr1 = w->fr1;
   wv.q0 = w->q0;
+  wv.qd0 = w->qd0;
+  wv.qd1 = w->qd1;
   wv.huge_u = w->huge_u;
   wv.huge_base = w->huge_base;
   wv.depth = depth;

@@ -112,7 +112,14 @@ __device__ void decide(const GView& g, const WView& w, const KParams& kp) {
     }
   }
   if (dir == kDirTD && next == kDirBU) c->bu_phases = c->bu_phases + 1;
-  c->aux = (!c->done && next == kDirTD) ? kAuxToQueue : kAuxNone;
+  /* a top-down level that appended its claims hands its queue on as is;
+     otherwise the next top-down level's queue is built from the bitmap */
+  const bool appended = dir == kDirTD && c->q_append;
+  const bool next_td = !c->done && next == kDirTD;
+  c->aux = (next_td && !appended) ? kAuxToQueue : kAuxNone;
+  c->q_direct = (next_td && appended) ? 1 : 0;
+  c->q_append = (next_td && mfn <= (int64_t)kDirectCap) ? 1 : 0;
+  c->qd_fill = 0ull;
   c->bu_run = bu_run;
   c->n_f = nfn;
   c->m_f = mfn;
@@ -149,22 +156,28 @@ __device__ __forceinline__ void store_labels(const WView& w, int32_t v, int32_t 
 /* Bookkeeping of a vertex v claimed from u (caller ID uc, or -1) at level L:
    labels, next-frontier bit and the degree sum that feeds the switching
    rule. */
-__device__ __forceinline__ void claimed(const GView& g, const WView& w, uint64_t* f_nxt, int32_t v, int32_t u,
-                                        int32_t uc, int32_t L, Acc& a) {
+__device__ __forceinline__ void claimed(const GView& g, const WView& w, uint64_t* f_nxt, int32_t* q_app, int32_t v,
+                                        int32_t u, int32_t uc, int32_t L, Acc& a) {
   store_labels(w, v, L + 1, u, uc);
   atomicOr(reinterpret_cast<unsigned long long*>(f_nxt + (v >> 6)), 1ull << (v & 63));
+  if (q_app) q_app[atomicAdd(&w.ctl->qd_fill, 1ull)] = v;
   a.found += 1;
   a.found_deg += g.off[v + 1] - g.off[v];
 }
 
-__device__ void top_down(const GView& g, const WView& w, const KParams& kp, int32_t L, Acc& a) {
+__device__ void top_down(const GView& g, const WView& w, const KParams& kp, int32_t L, uint32_t nblocks, Acc& a) {
   Ctl* c = w.ctl;
   const int64_t nf = c->n_f;
-  const int32_t* q_cur = w.q0;
+  const int32_t* q_cur = c->q_direct ? ((L & 1) ? w.qd1 : w.qd0) : w.q0;
+  uint64_t* f_cur = (L & 1) ? w.fr1 : w.fr0;
   uint64_t* f_nxt = (L & 1) ? w.fr0 : w.fr1;
+  /* a small level appends its claims to the next queue and clears its own
+     frontier bits, leaving that buffer empty for the next level to fill */
+  const bool append = c->q_append != 0;
+  int32_t* q_app = append ? ((L & 1) ? w.qd0 : w.qd1) : nullptr;
   const int lane = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int64_t nwaves = ((int64_t)nblocks * blockDim.x) / kWave;
   const int64_t wave_cut = kp.td_wave_cut, huge_cut = kp.td_huge_cut;
 
   for (int64_t base = wave * kWave; base < nf; base += nwaves * kWave) {
@@ -177,6 +190,7 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
       beg = g.off[u];
       deg = g.off[u + 1] - beg;
       if (g.new2old) uc = g.new2old[u]; /* one lookup per frontier vertex, not per claim */
+      if (append) atomicAnd(reinterpret_cast<unsigned long long*>(f_cur + (u >> 6)), ~(1ull << (u & 63)));
     }
     a.checked += deg;
     const bool huge = valid && deg > huge_cut;
@@ -186,7 +200,7 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
     const int64_t sdeg = (valid && !huge && !med) ? deg : 0;
     for (int64_t j = 0; j < sdeg; ++j) {
       const int32_t v = g.idx[beg + j];
-      if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, u, uc, L, a);
+      if (try_claim(w.vis, v)) claimed(g, w, f_nxt, q_app, v, u, uc, L, a);
     }
 
     /* wavefront per vertex */
@@ -199,7 +213,7 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
       const int64_t dd = __shfl(deg, src);
       for (int64_t k = lane; k < dd; k += kWave) {
         const int32_t v = g.idx[bb + k];
-        if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, uu, uuc, L, a);
+        if (try_claim(w.vis, v)) claimed(g, w, f_nxt, q_app, v, uu, uuc, L, a);
       }
     }
 
@@ -353,10 +367,18 @@ __device__ __forceinline__ void level_body(const GView& g, const WView& w, const
   Ctl* c = w.ctl;
   if (c->done || c->aux != kAuxNone || c->dir != want_dir) return;
   const int32_t L = c->level;
+  /* a top-down level needs only enough workgroups for one queue entry per
+     thread; the others leave before the completion count */
+  uint32_t nb = gridDim.x;
+  if (want_dir == kDirTD) {
+    const int64_t need = (c->n_f + kBlock - 1) / kBlock;
+    if (need < (int64_t)nb) nb = need < 1 ? 1u : (uint32_t)need;
+    if (blockIdx.x >= nb) return;
+  }
   Acc a = {0, 0, 0, 0};
-  if (want_dir == kDirTD) top_down(g, w, kp, L, a);
+  if (want_dir == kDirTD) top_down(g, w, kp, L, nb, a);
   else bottom_up(g, w, kp, L, a);
-  if (finish_block(c, a)) {
+  if (finish_block(c, a, nb)) {
     if (want_dir == kDirTD && ld_agent(&c->huge_pack) != 0ull) {
       c->aux = kAuxHuge;
     } else {
@@ -428,12 +450,13 @@ __global__ void __launch_bounds__(kBlock) k_aux(GView g, WView w, KParams kp) {
       while (lo + 1 < nent && (int64_t)w.huge_base[lo + 1] <= ch) ++lo;
       const int32_t u = w.huge_u[lo];
       const int32_t uc = g.new2old ? g.new2old[u] : -1;
+      int32_t* q_app = c->q_append ? ((L & 1) ? w.qd0 : w.qd1) : nullptr;
       const int64_t rb = g.off[u], re = g.off[u + 1];
       const int64_t beg = rb + (ch - (int64_t)w.huge_base[lo]) * kHugeChunk;
       const int64_t end = min(re, beg + (int64_t)kHugeChunk);
       for (int64_t k = beg + lane; k < end; k += kWave) {
         const int32_t v = g.idx[k];
-        if (try_claim(w.vis, v)) claimed(g, w, f_nxt, v, u, uc, L, a);
+        if (try_claim(w.vis, v)) claimed(g, w, f_nxt, q_app, v, u, uc, L, a);
       }
     }
     if (finish_block(c, a)) {
@@ -545,6 +568,9 @@ __global__ void __launch_bounds__(kBlock) k_init_roots(GView g, WView w, const i
   c->scanned = 0;
   c->huge_pack = 0ull;
   c->q_fill = 0;
+  c->q_direct = 0;
+  c->q_append = (first_dir == kDirTD && dr <= (int64_t)kDirectCap) ? 1 : 0;
+  c->qd_fill = 0ull;
   c->reached = s_cnt;
   c->reached_deg = dr;
   c->checked_total = 0;

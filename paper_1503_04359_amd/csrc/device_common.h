@@ -45,11 +45,12 @@ __device__ __forceinline__ T ld_agent(const T* p) {
 
 /* End of a workgroup's share of a level kernel: its accumulators are summed
    and handed on, and the call returns true in thread 0 of the last
-   workgroup of the grid.  Workgroups report to one of kGroups group slots
+   workgroup of the grid (or of its first `nblocks` workgroups, when only
+   those take part).  Workgroups report to one of kGroups group slots
    (one cache line each) and the last of each group forwards the group's sums
    to the level counters, so no address sees more than gridDim/kGroups
    atomics. */
-__device__ bool finish_block(Ctl* c, Acc a) {
+__device__ bool finish_block(Ctl* c, Acc a, uint32_t nblocks = 0) {
   __shared__ int64_t part[4][kBlock / kWave];
   __shared__ unsigned long long bpart[kBlock / kWave];
   __shared__ int is_last;
@@ -73,9 +74,10 @@ __device__ bool finish_block(Ctl* c, Acc a) {
     for (int k = 0; k < 4; ++k)
       for (int j = 0; j < kBlock / kWave; ++j) sum[k] += part[k][j];
     for (int j = 0; j < kBlock / kWave; ++j) bits |= bpart[j];
-    const uint32_t ng = gridDim.x < (uint32_t)kGroups ? gridDim.x : (uint32_t)kGroups;
+    const uint32_t nb = nblocks ? nblocks : gridDim.x; /* workgroups taking part */
+    const uint32_t ng = nb < (uint32_t)kGroups ? nb : (uint32_t)kGroups;
     const uint32_t grp = blockIdx.x % ng;
-    const uint32_t gsize = (gridDim.x - grp + ng - 1) / ng;
+    const uint32_t gsize = (nb - grp + ng - 1) / ng;
     GroupSlot& gs = c->grp[grp];
     for (int k = 0; k < 4; ++k)
       if (sum[k]) atomicAdd(reinterpret_cast<unsigned long long*>(&gs.sum[k]), (unsigned long long)sum[k]);

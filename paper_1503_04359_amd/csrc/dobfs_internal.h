@@ -50,7 +50,10 @@ constexpr int kMsPullSplit = 2048;   /* batched pull: degree above which a verte
 constexpr int kMsPullProbe = 512;    /* batched pull: entries such a vertex scans before it is split */
 constexpr int kMsTake = 256;         /* batched push: entries per row and round */
 
-constexpr int kGroups = 16;
+constexpr int kGroups = 64;
+constexpr int kDirectCap = 1 << 16;  /* entries of a direct queue; a top-down level whose
+                                        frontier has at most this many edges appends its
+                                        claims to the next level's queue itself */
 constexpr int kXcds = 8;             /* dies (XCDs) of an MI355X; workgroups are dealt round-robin */
 constexpr int kMaxSeg = 72;          /* degree classes of int64 degrees, plus one */
 constexpr int kFinBlock = 4096;      /* minimum caller IDs per finalize workgroup */
@@ -106,6 +109,10 @@ struct Ctl {
   int32_t active_slots;         /* slots being served                        */
   int32_t pad3;
   unsigned long long pull_mask; /* batched: slots pulled (bottom-up) in level L */
+  /* small top-down levels hand their queue on directly */
+  int32_t q_append;     /* top-down level L appends its claims to the next queue */
+  int32_t q_direct;     /* level L's queue is a direct buffer, not q0            */
+  unsigned long long qd_fill; /* append cursor of the next queue               */
   GroupSlot grp[kGroups]; /* zero between kernels */
   SlotStat slot[64];      /* batched: per-slot counters                      */
 };
@@ -141,6 +148,8 @@ struct WView {
   uint64_t* fr0;
   uint64_t* fr1;
   int32_t* q0;          /* frontier queue of a top-down level            */
+  int32_t* qd0;         /* direct queues (kDirectCap entries), level parity */
+  int32_t* qd1;
   int32_t* huge_u;
   uint32_t* huge_base;
   int32_t* depth;         /* caller's outputs (caller labels)              */
