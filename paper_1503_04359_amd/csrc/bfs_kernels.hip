@@ -167,13 +167,15 @@ __device__ __forceinline__ void claimed(const GView& g, const WView& w, uint64_t
 
 __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int32_t L, uint32_t nblocks, Acc& a) {
   Ctl* c = w.ctl;
-  const int64_t nf = c->n_f;
-  const int32_t* q_cur = c->q_direct ? ((L & 1) ? w.qd1 : w.qd0) : w.q0;
+  /* control fields may have been written by this workgroup's own previous
+     level (see level_body): read them from L2 */
+  const int64_t nf = ld_agent(&c->n_f);
+  const int32_t* q_cur = ld_agent(&c->q_direct) ? ((L & 1) ? w.qd1 : w.qd0) : w.q0;
   uint64_t* f_cur = (L & 1) ? w.fr1 : w.fr0;
   uint64_t* f_nxt = (L & 1) ? w.fr0 : w.fr1;
   /* a small level appends its claims to the next queue and clears its own
      frontier bits, leaving that buffer empty for the next level to fill */
-  const bool append = c->q_append != 0;
+  const bool append = ld_agent(&c->q_append) != 0;
   int32_t* q_app = append ? ((L & 1) ? w.qd0 : w.qd1) : nullptr;
   const int lane = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -365,25 +367,39 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
    the one whose direction is not the level's returns at once. */
 __device__ __forceinline__ void level_body(const GView& g, const WView& w, const KParams& kp, int32_t want_dir) {
   Ctl* c = w.ctl;
-  if (c->done || c->aux != kAuxNone || c->dir != want_dir) return;
-  const int32_t L = c->level;
-  /* a top-down level needs only enough workgroups for one queue entry per
-     thread; the others leave before the completion count */
-  uint32_t nb = gridDim.x;
-  if (want_dir == kDirTD) {
-    const int64_t need = (c->n_f + kBlock - 1) / kBlock;
-    if (need < (int64_t)nb) nb = need < 1 ? 1u : (uint32_t)need;
-    if (blockIdx.x >= nb) return;
-  }
-  Acc a = {0, 0, 0, 0};
-  if (want_dir == kDirTD) top_down(g, w, kp, L, nb, a);
-  else bottom_up(g, w, kp, L, a);
-  if (finish_block(c, a, nb)) {
-    if (want_dir == kDirTD && ld_agent(&c->huge_pack) != 0ull) {
-      c->aux = kAuxHuge;
-    } else {
-      decide(g, w, kp);
+  /* A top-down level needs only enough workgroups for one queue entry per
+     thread; the others leave before the completion count.  When that is a
+     single workgroup and the next level is again a small top-down level
+     with its queue handed on directly, the workgroup goes straight on to
+     it: long chains of tiny levels (path-like tails) cost a barrier each
+     instead of a launch sequence each. */
+  for (;;) {
+    if (ld_agent(&c->done) || ld_agent(&c->aux) != kAuxNone || ld_agent(&c->dir) != want_dir) return;
+    const int32_t L = ld_agent(&c->level);
+    uint32_t nb = gridDim.x;
+    if (want_dir == kDirTD) {
+      const int64_t need = (ld_agent(&c->n_f) + kBlock - 1) / kBlock;
+      if (need < (int64_t)nb) nb = need < 1 ? 1u : (uint32_t)need;
+      if (blockIdx.x >= nb) return;
     }
+    Acc a = {0, 0, 0, 0};
+    if (want_dir == kDirTD) top_down(g, w, kp, L, nb, a);
+    else bottom_up(g, w, kp, L, a);
+    if (finish_block(c, a, nb)) {
+      if (want_dir == kDirTD && ld_agent(&c->huge_pack) != 0ull) {
+        c->aux = kAuxHuge;
+      } else {
+        decide(g, w, kp);
+      }
+    }
+    if (want_dir != kDirTD || nb != 1) return;
+    /* make thread 0's control writes and every thread's labels, bits and
+       queue entries of this level visible to the whole workgroup */
+    __threadfence();
+    __syncthreads();
+    __threadfence();
+    /* only while the next level also fits this one workgroup */
+    if (!ld_agent(&c->q_direct) || ld_agent(&c->n_f) > (int64_t)kBlock) return;
   }
 }
 

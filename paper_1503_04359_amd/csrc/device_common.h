@@ -75,35 +75,44 @@ __device__ bool finish_block(Ctl* c, Acc a, uint32_t nblocks = 0) {
       for (int j = 0; j < kBlock / kWave; ++j) sum[k] += part[k][j];
     for (int j = 0; j < kBlock / kWave; ++j) bits |= bpart[j];
     const uint32_t nb = nblocks ? nblocks : gridDim.x; /* workgroups taking part */
-    const uint32_t ng = nb < (uint32_t)kGroups ? nb : (uint32_t)kGroups;
-    const uint32_t grp = blockIdx.x % ng;
-    const uint32_t gsize = (nb - grp + ng - 1) / ng;
-    GroupSlot& gs = c->grp[grp];
-    for (int k = 0; k < 4; ++k)
-      if (sum[k]) atomicAdd(reinterpret_cast<unsigned long long*>(&gs.sum[k]), (unsigned long long)sum[k]);
-    if (bits) atomicOr(&gs.bits, bits);
-    __threadfence();
-    bool last = false;
-    if (atomicAdd(&gs.ticket, 1u) == gsize - 1) {
+    if (nb == 1) { /* alone: no other workgroup to wait for or to race with */
+      c->nf_next += sum[0];
+      c->mf_next += sum[1];
+      c->checked += sum[2];
+      c->scanned += sum[3];
+      c->live_next |= bits;
+      is_last = 1;
+    } else {
+      const uint32_t ng = nb < (uint32_t)kGroups ? nb : (uint32_t)kGroups;
+      const uint32_t grp = blockIdx.x % ng;
+      const uint32_t gsize = (nb - grp + ng - 1) / ng;
+      GroupSlot& gs = c->grp[grp];
+      for (int k = 0; k < 4; ++k)
+        if (sum[k]) atomicAdd(reinterpret_cast<unsigned long long*>(&gs.sum[k]), (unsigned long long)sum[k]);
+      if (bits) atomicOr(&gs.bits, bits);
       __threadfence();
-      int64_t* tot[4] = {&c->nf_next, &c->mf_next, &c->checked, &c->scanned};
-      for (int k = 0; k < 4; ++k) {
-        const int64_t v = ld_agent(&gs.sum[k]);
-        gs.sum[k] = 0;
-        if (v) atomicAdd(reinterpret_cast<unsigned long long*>(tot[k]), (unsigned long long)v);
-      }
-      const unsigned long long gb = ld_agent(&gs.bits);
-      gs.bits = 0ull;
-      if (gb) atomicOr(&c->live_next, gb);
-      gs.ticket = 0;
-      __threadfence();
-      last = atomicAdd(&c->ticket, 1u) == ng - 1;
-      if (last) {
-        c->ticket = 0;
+      bool last = false;
+      if (atomicAdd(&gs.ticket, 1u) == gsize - 1) {
         __threadfence();
+        int64_t* tot[4] = {&c->nf_next, &c->mf_next, &c->checked, &c->scanned};
+        for (int k = 0; k < 4; ++k) {
+          const int64_t v = ld_agent(&gs.sum[k]);
+          gs.sum[k] = 0;
+          if (v) atomicAdd(reinterpret_cast<unsigned long long*>(tot[k]), (unsigned long long)v);
+        }
+        const unsigned long long gb = ld_agent(&gs.bits);
+        gs.bits = 0ull;
+        if (gb) atomicOr(&c->live_next, gb);
+        gs.ticket = 0;
+        __threadfence();
+        last = atomicAdd(&c->ticket, 1u) == ng - 1;
+        if (last) {
+          c->ticket = 0;
+          __threadfence();
+        }
       }
+      is_last = last;
     }
-    is_last = last;
   }
   __syncthreads();
   return threadIdx.x == 0 && is_last;
