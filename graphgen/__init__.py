@@ -275,6 +275,7 @@ def _load_device():
         return _dlib
     if not os.path.exists(_DLIB_PATH):
         raise ImportError(f"{_DLIB_PATH} is missing: build it first (python graphgen/_build.py)")
+    import torch  # noqa: F401  (the HIP runtime the device builder shares; see the binding)
     lib = ctypes.CDLL(_DLIB_PATH)
     P = ctypes.POINTER
     lib.ggd_kronecker.restype = ctypes.c_int

@@ -22,6 +22,11 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it first (python __graft_entry__.py build, "
         "or python paper_1503_04359_amd/_build.py)")
 
+# torch first: it brings the process's HIP runtime, which the library then
+# shares; loading the library first would start a second runtime that sees
+# no device once torch's is up.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- status codes and flags (include/dobfs.h) ------------------------------

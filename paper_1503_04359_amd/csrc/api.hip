@@ -171,7 +171,7 @@ int alloc_workspace(dobfs_graph_s* g, Workspace* w) {
   const int64_t W = g->words;
   hipError_t e;
   if ((e = dalloc(&w->vis, W)) != hipSuccess || (e = dalloc(&w->fr0, W)) != hipSuccess ||
-      (e = dalloc(&w->fr1, W)) != hipSuccess || (e = dalloc(&w->q0, g->n)) != hipSuccess ||
+      (e = dalloc(&w->fr1, W)) != hipSuccess || (e = dalloc(&w->q0, std::max(g->n, 4 * W))) != hipSuccess ||
       (e = dalloc(&w->qd0, kDirectCap)) != hipSuccess || (e = dalloc(&w->qd1, kDirectCap)) != hipSuccess ||
       (e = dalloc(&w->huge_u, g->n_huge)) != hipSuccess ||
       (e = dalloc(&w->huge_base, g->n_huge)) != hipSuccess || (e = dalloc(&w->ctl, 1)) != hipSuccess ||

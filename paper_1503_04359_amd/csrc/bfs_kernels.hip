@@ -269,22 +269,68 @@ __device__ __forceinline__ void resolve_chunk(uint64_t H, int c0, int excl, int 
   }
 }
 
-/* Bottom-up level.  One wavefront per 64-vertex word.  Round 0: every
-   unvisited vertex tests its first neighbour (its highest-degree one on a
-   relabelled graph), one lane per vertex.  Later rounds: each vertex still
+/* Rounds after round 0 for one word of a bottom-up level: each vertex still
    searching contributes its next min(2^r, remaining) neighbours, the
    contributions are laid end to end and cut into 64-entry chunks (two
    chunks in flight at a time), and each lane tests one neighbour.  Every
    lane does useful work even when degrees differ inside the word, one
    vertex's neighbour IDs are read contiguously, and a vertex stops at the
    round in which it meets its first frontier neighbour (its parent: the
-   first hit in adjacency order).  The next word's visited bits are loaded
-   one iteration ahead. */
+   first hit in adjacency order). */
+__device__ __forceinline__ void bu_rounds(const GView& g, const uint64_t* f_cur, int max_quota, int64_t pos,
+                                          int64_t end, bool& found, int32_t& par, int32_t& n_checked) {
+  const int lane = lane_id();
+  int quota = 2;
+  while (__ballot(!found && pos < end)) {
+    const int take = (!found && pos < end) ? (int)min(end - pos, (int64_t)quota) : 0;
+    const int incl = wave_incl_scan(take, lane);
+    const int excl = incl - take;
+    const int total = __shfl(incl, kWave - 1);
+    for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
+      const int p1 = c0 + lane, p2 = c0 + kWave + lane;
+      const int o1 = owner_of(incl, p1), o2 = owner_of(incl, p2);
+      const int64_t e1 = __shfl(pos, o1) + (p1 - __shfl(excl, o1));
+      const int64_t e2 = __shfl(pos, o2) + (p2 - __shfl(excl, o2));
+      int32_t u1 = 0, u2 = 0;
+      if (p1 < total) u1 = g.idx[e1];
+      if (p2 < total) u2 = g.idx[e2];
+      const bool h1 = p1 < total && test_bit(f_cur, u1);
+      const bool h2 = p2 < total && test_bit(f_cur, u2);
+      const uint64_t H1 = __ballot(h1), H2 = __ballot(h2);
+      resolve_chunk(H1, c0, excl, incl, take, u1, found, par, n_checked);
+      resolve_chunk(H2, c0 + kWave, excl, incl, take, u2, found, par, n_checked);
+    }
+    pos += take;
+    if (quota < max_quota) quota <<= 1;
+  }
+}
+
+/* Bottom-up level, in two passes over the same words, each wavefront
+   keeping its own words in both (so the second pass reads only what the
+   same wavefront wrote in the first).
+
+   Pass 1 takes kBuWords consecutive 64-vertex words at a time; lane i owns
+   vertex 64w+i of each.  Round 0 of all of them is issued together, so that
+   their dependent loads (visited word, row bounds and first neighbour,
+   frontier bit, the parent's caller ID) overlap instead of following one
+   another word by word: every unvisited vertex tests its first neighbour
+   (its highest-degree one on a relabelled graph), read from the
+   first-neighbour column in one coalesced load.  A word whose vertices all
+   settle here is finished at once; for a word with vertices left to search,
+   the round-0 hits and the searching vertices are recorded as two masks in
+   the queue buffer, which bottom-up levels do not otherwise use.
+
+   Pass 2 runs the later rounds (bu_rounds) for the recorded words, one
+   word at a time, and finishes them.  Splitting the passes keeps each within
+   64 registers: round 0 of several words and the rounds' own state are
+   never live together. */
 __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int32_t L, Acc& a) {
+  constexpr int K = kBuWords;
   const uint64_t* f_cur = (L & 1) ? w.fr1 : w.fr0;
   uint64_t* f_nxt = (L & 1) ? w.fr0 : w.fr1;
+  uint64_t* rec = reinterpret_cast<uint64_t*>(w.q0);  /* word wd: [2wd] hits, [2wd+1] searching */
   const int lane = lane_id();
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t wave = wave_index();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const int max_quota = kp.bu_heavy_cut < kWave ? kWave : kp.bu_heavy_cut;
   const int64_t W = g.words_active;
@@ -292,69 +338,133 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
      level); they join the 64-bit accumulators once at the end */
   int32_t n_scanned = 0, n_checked = 0, n_found = 0;
 
-  uint64_t vis_next = wave < W ? w.vis[wave] : ~0ull;
-  for (int64_t wd = wave; wd < W; wd += nwaves) {
-    const uint64_t vis = vis_next;
-    if (wd + nwaves < W) vis_next = w.vis[wd + nwaves];
-    if (vis == ~0ull) {
-      if (lane == 0) f_nxt[wd] = 0ull;
+  /* ---- pass 1: round 0 ---- */
+  /* the next group's visited words are loaded one iteration ahead; the
+     load is unconditional (an idle lane reads an in-bounds word) and its
+     value is masked only when used, so nothing waits for it early */
+  bool ok_next = lane < K && wave * K + lane < W;
+  uint64_t raw_next = w.vis[ok_next ? wave * K + lane : 0];
+  for (int64_t wb = wave * K; wb < W; wb += nwaves * K) {
+    const uint64_t vis_mine = ok_next ? raw_next : ~0ull;  /* lanes 0..K-1: word wb+lane */
+    {
+      const int64_t nx = wb + nwaves * K + lane;
+      ok_next = lane < K && nx < W;
+      raw_next = w.vis[ok_next ? nx : wb];
+    }
+    if (!__ballot(lane < K && vis_mine != ~0ull)) {
+      if (lane < K && wb + lane < W) {
+        f_nxt[wb + lane] = 0ull;
+        rec[2 * (wb + lane) + 1] = 0ull;
+      }
       continue;
     }
-    const int32_t v = (int32_t)(wd * kWave + lane);
-    const bool unv = ((vis >> lane) & 1ull) == 0ull;  /* bits >= n are set */
-    int64_t pos = 0, end = 0;
-    if (unv) {
-      pos = g.off[v];
-      end = g.off[v + 1];
+    /* Every load is issued before any is used, and none sits under a
+       branch (lanes with nothing to load read entry 0 of the word group,
+       which is in bounds), so the compiler can wait for each one alone
+       instead of for everything outstanding.  Addresses are a wave-uniform
+       base plus a 32-bit lane offset. */
+    const int64_t v0 = wb * kWave;
+    const uint32_t* off_lo = reinterpret_cast<const uint32_t*>(g.off + v0);
+    const int32_t* first = g.first + v0;
+    const uint32_t* f32 = reinterpret_cast<const uint32_t*>(f_cur);
+    uint32_t b[K], e[K], fw[K];
+    int32_t u0[K];
+    bool unv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint64_t vw = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(vis_mine >> 32), k) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)vis_mine, k);
+      unv[k] = ((vw >> lane) & 1ull) == 0ull;  /* bits >= n are set */
     }
-    const int64_t deg = end - pos;
-    n_scanned += unv ? 1 : 0;
-    bool found = false, hit0 = false;
-    int32_t par = -1;
-    /* round 0: own first neighbour, from the first-neighbour column (one
-       coalesced read instead of a line per row) */
-    if (pos < end) {
-      const int32_t u = g.first[v];
-      n_checked += 1;
-      if (test_bit(f_cur, u)) {
-        found = hit0 = true;
-        par = u;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = unv[k] ? k * kWave + lane : 0;
+      /* degrees fit in 31 bits, so the low words of the row bounds give
+         the degree */
+      b[k] = off_lo[2 * i];
+      e[k] = off_lo[2 * i + 2];
+      u0[k] = first[i];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (!unv[k]) e[k] = b[k];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t u = e[k] != b[k] ? (uint32_t)u0[k] : 0u;
+      fw[k] = f32[u >> 5];
+    }
+    uint32_t hit = 0u;
+    int32_t pc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int32_t deg = (int32_t)(e[k] - b[k]);
+      if (deg > 0 && ((fw[k] >> (u0[k] & 31)) & 1u)) hit |= 1u << k;
+      n_scanned += unv[k] ? 1 : 0;
+      n_checked += deg > 0 ? 1 : 0;
+      /* the first neighbour's caller ID is in the matching column */
+      pc[k] = -1;
+      if (g.first_caller) pc[k] = g.first_caller[v0 + (((hit >> k) & 1u) ? k * kWave + lane : 0)];
+    }
+    uint64_t my_hit = 0ull, my_srch = 0ull;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int32_t deg = (int32_t)(e[k] - b[k]);
+      const bool h = (hit >> k) & 1u;
+      if (h) {
+        store_labels(w, (int32_t)(v0 + k * kWave + lane), L + 1, u0[k], pc[k]);
+        a.found_deg += deg;
+        n_found += 1;
       }
-      ++pos;
-    }
-    int quota = 2;
-    while (__ballot(!found && pos < end)) {
-      const int take = (!found && pos < end) ? (int)min(end - pos, (int64_t)quota) : 0;
-      const int incl = wave_incl_scan(take, lane);
-      const int excl = incl - take;
-      const int total = __shfl(incl, kWave - 1);
-      for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
-        const int p1 = c0 + lane, p2 = c0 + kWave + lane;
-        const int o1 = owner_of(incl, p1), o2 = owner_of(incl, p2);
-        const int64_t e1 = __shfl(pos, o1) + (p1 - __shfl(excl, o1));
-        const int64_t e2 = __shfl(pos, o2) + (p2 - __shfl(excl, o2));
-        int32_t u1 = 0, u2 = 0;
-        if (p1 < total) u1 = g.idx[e1];
-        if (p2 < total) u2 = g.idx[e2];
-        const bool h1 = p1 < total && test_bit(f_cur, u1);
-        const bool h2 = p2 < total && test_bit(f_cur, u2);
-        const uint64_t H1 = __ballot(h1), H2 = __ballot(h2);
-        resolve_chunk(H1, c0, excl, incl, take, u1, found, par, n_checked);
-        resolve_chunk(H2, c0 + kWave, excl, incl, take, u2, found, par, n_checked);
+      const uint64_t hm = __ballot(h), sm = __ballot(!h && deg > 1);
+      if (lane == k) {
+        my_hit = hm;
+        my_srch = sm;
       }
-      pos += take;
-      if (quota < max_quota) quota <<= 1;
     }
-    const uint64_t fm = __ballot(found);
-    if (found) {
-      /* a round-0 parent's caller ID is in the matching column */
-      store_labels(w, v, L + 1, par, (hit0 && g.first_caller) ? g.first_caller[v] : -1);
-      a.found_deg += deg;
-      n_found += 1;
+    if (lane < K && wb + lane < W) {
+      const int64_t wd = wb + lane;
+      rec[2 * wd + 1] = my_srch;
+      if (my_srch) {
+        rec[2 * wd] = my_hit;  /* finished in pass 2 */
+      } else {
+        f_nxt[wd] = my_hit;
+        if (my_hit) w.vis[wd] = vis_mine | my_hit;
+      }
     }
-    if (lane == 0) {
-      f_nxt[wd] = fm;
-      if (fm) w.vis[wd] = vis | fm;
+  }
+
+  /* ---- pass 2: later rounds of the recorded words ---- */
+  for (int64_t wb = wave * K; wb < W; wb += nwaves * K) {
+    const uint64_t srch_mine = (lane < K && wb + lane < W) ? rec[2 * (wb + lane) + 1] : 0ull;
+    if (!__ballot(srch_mine != 0ull)) continue;
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) {
+      const uint64_t sm = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(srch_mine >> 32), k) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)srch_mine, k);
+      if (!sm) continue;
+      const int64_t wd = wb + k;
+      const int32_t v = (int32_t)(wd * kWave + lane);
+      const bool s = (sm >> lane) & 1ull;
+      int64_t pos = 0, end = 0;
+      if (s) {
+        pos = g.off[v] + 1;  /* round 0 tested the first entry */
+        end = g.off[v + 1];
+      }
+      bool found = !s;  /* only searching lanes take part */
+      int32_t par = -1;
+      bu_rounds(g, f_cur, max_quota, pos, end, found, par, n_checked);
+      const bool got = s && found;
+      if (got) {
+        store_labels(w, v, L + 1, par);
+        a.found_deg += end - (pos - 1);
+        n_found += 1;
+      }
+      const uint64_t fm = __ballot(got);
+      if (lane == 0) {
+        const uint64_t all = rec[2 * wd] | fm;
+        f_nxt[wd] = all;
+        if (all) w.vis[wd] |= all;
+      }
     }
   }
   a.scanned += n_scanned;

@@ -16,6 +16,12 @@ __device__ __forceinline__ int lane_id() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
 }
 
+/* Global wavefront index, made wave-uniform for the compiler so that
+   values derived from it live in scalar registers. */
+__device__ __forceinline__ int64_t wave_index() {
+  return (int64_t)blockIdx.x * (blockDim.x / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
+
 __device__ __forceinline__ bool test_bit(const uint64_t* bm, int32_t v) {
   return (bm[v >> 6] >> (v & 63)) & 1ull;
 }

@@ -31,6 +31,7 @@ def test_header_declares_the_boundary():
 def test_library_exports_every_declared_symbol():
     import __graft_entry__
     __graft_entry__.ensure_built()
+    import torch  # noqa: F401  (its HIP runtime first, as the binding does)
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1503_04359_amd", "libdobfs.so"))
     missing = [n for n in _declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
