@@ -277,8 +277,20 @@ __device__ __forceinline__ void resolve_chunk(uint64_t H, int c0, int excl, int 
    vertex's neighbour IDs are read contiguously, and a vertex stops at the
    round in which it meets its first frontier neighbour (its parent: the
    first hit in adjacency order). */
-__device__ __forceinline__ void bu_rounds(const GView& g, const uint64_t* f_cur, int max_quota, int64_t pos,
-                                          int64_t end, bool& found, int32_t& par, int32_t& n_checked) {
+/* Frontier bit of u: from the workgroup's LDS copy of the bitmap's first
+   kBuHot32 words when u falls there, else from the bitmap.  Both loads are
+   issued (the other one at a shared, in-bounds address) so that no load sits
+   under a branch. */
+__device__ __forceinline__ uint32_t frontier_word(const uint32_t* hot, const uint32_t* f32, uint32_t u) {
+  const uint32_t wi = u >> 5;
+  const bool in_hot = wi < (uint32_t)kBuHot32;
+  const uint32_t h = hot[in_hot ? wi : 0u];
+  const uint32_t gw = f32[in_hot ? 0u : wi];
+  return in_hot ? h : gw;
+}
+
+__device__ __forceinline__ void bu_rounds(const GView& g, const uint32_t* hot, const uint32_t* f32, int max_quota,
+                                          int64_t pos, int64_t end, bool& found, int32_t& par, int32_t& n_checked) {
   const int lane = lane_id();
   int quota = 2;
   while (__ballot(!found && pos < end)) {
@@ -294,8 +306,8 @@ __device__ __forceinline__ void bu_rounds(const GView& g, const uint64_t* f_cur,
       int32_t u1 = 0, u2 = 0;
       if (p1 < total) u1 = g.idx[e1];
       if (p2 < total) u2 = g.idx[e2];
-      const bool h1 = p1 < total && test_bit(f_cur, u1);
-      const bool h2 = p2 < total && test_bit(f_cur, u2);
+      const bool h1 = p1 < total && ((frontier_word(hot, f32, (uint32_t)u1) >> (u1 & 31)) & 1u);
+      const bool h2 = p2 < total && ((frontier_word(hot, f32, (uint32_t)u2) >> (u2 & 31)) & 1u);
       const uint64_t H1 = __ballot(h1), H2 = __ballot(h2);
       resolve_chunk(H1, c0, excl, incl, take, u1, found, par, n_checked);
       resolve_chunk(H2, c0 + kWave, excl, incl, take, u2, found, par, n_checked);
@@ -337,6 +349,16 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
   /* per-lane counts in 32 bits (a lane sees far fewer than 2^31 entries per
      level); they join the 64-bit accumulators once at the end */
   int32_t n_scanned = 0, n_checked = 0, n_found = 0;
+  /* The start of the frontier bitmap is staged in LDS: on a relabelled
+     graph it holds the highest-degree vertices, which most probes hit (a
+     vertex's neighbours are scanned highest degree first), and an LDS read
+     spares the vector cache a scattered line access.  Words past the active
+     range read as zero; no probe reaches them (isolated vertices are no
+     one's neighbours). */
+  __shared__ uint32_t hot[kBuHot32];
+  const uint32_t* f32 = reinterpret_cast<const uint32_t*>(f_cur);
+  for (int i = threadIdx.x; i < kBuHot32; i += blockDim.x) hot[i] = i < 2 * W ? f32[i] : 0u;
+  __syncthreads();
 
   /* ---- pass 1: round 0 ---- */
   /* the next group's visited words are loaded one iteration ahead; the
@@ -366,9 +388,8 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
     const int64_t v0 = wb * kWave;
     const uint32_t* off_lo = reinterpret_cast<const uint32_t*>(g.off + v0);
     const int32_t* first = g.first + v0;
-    const uint32_t* f32 = reinterpret_cast<const uint32_t*>(f_cur);
     uint32_t b[K], e[K], fw[K];
-    int32_t u0[K];
+    int32_t u0[K], pcr[K];
     bool unv[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -384,6 +405,9 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
       b[k] = off_lo[2 * i];
       e[k] = off_lo[2 * i + 2];
       u0[k] = first[i];
+      /* the first neighbour's caller ID, in case it is the parent: loaded
+         with the rest rather than after the frontier test */
+      pcr[k] = g.first_caller ? g.first_caller[v0 + i] : -1;
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -391,19 +415,15 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const uint32_t u = e[k] != b[k] ? (uint32_t)u0[k] : 0u;
-      fw[k] = f32[u >> 5];
+      fw[k] = frontier_word(hot, f32, u);
     }
     uint32_t hit = 0u;
-    int32_t pc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int32_t deg = (int32_t)(e[k] - b[k]);
       if (deg > 0 && ((fw[k] >> (u0[k] & 31)) & 1u)) hit |= 1u << k;
       n_scanned += unv[k] ? 1 : 0;
       n_checked += deg > 0 ? 1 : 0;
-      /* the first neighbour's caller ID is in the matching column */
-      pc[k] = -1;
-      if (g.first_caller) pc[k] = g.first_caller[v0 + (((hit >> k) & 1u) ? k * kWave + lane : 0)];
     }
     uint64_t my_hit = 0ull, my_srch = 0ull;
 #pragma unroll
@@ -411,7 +431,7 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
       const int32_t deg = (int32_t)(e[k] - b[k]);
       const bool h = (hit >> k) & 1u;
       if (h) {
-        store_labels(w, (int32_t)(v0 + k * kWave + lane), L + 1, u0[k], pc[k]);
+        store_labels(w, (int32_t)(v0 + k * kWave + lane), L + 1, u0[k], pcr[k]);
         a.found_deg += deg;
         n_found += 1;
       }
@@ -452,7 +472,7 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
       }
       bool found = !s;  /* only searching lanes take part */
       int32_t par = -1;
-      bu_rounds(g, f_cur, max_quota, pos, end, found, par, n_checked);
+      bu_rounds(g, hot, f32, max_quota, pos, end, found, par, n_checked);
       const bool got = s && found;
       if (got) {
         store_labels(w, v, L + 1, par);
