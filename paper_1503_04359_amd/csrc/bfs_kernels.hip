@@ -495,6 +495,7 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
 /* The level kernels: top-down and bottom-up are separate kernels, both
    launched for every level, so that each gets its own register allocation;
    the one whose direction is not the level's returns at once. */
+template <int BT>
 __device__ __forceinline__ void level_body(const GView& g, const WView& w, const KParams& kp, int32_t want_dir) {
   Ctl* c = w.ctl;
   /* A top-down level needs only enough workgroups for one queue entry per
@@ -515,7 +516,7 @@ __device__ __forceinline__ void level_body(const GView& g, const WView& w, const
     Acc a = {0, 0, 0, 0};
     if (want_dir == kDirTD) top_down(g, w, kp, L, nb, a);
     else bottom_up(g, w, kp, L, a);
-    if (finish_block(c, a, nb)) {
+    if (finish_block<BT>(c, a, nb)) {
       if (want_dir == kDirTD && ld_agent(&c->huge_pack) != 0ull) {
         c->aux = kAuxHuge;
       } else {
@@ -534,11 +535,13 @@ __device__ __forceinline__ void level_body(const GView& g, const WView& w, const
 }
 
 __global__ void __launch_bounds__(kBlock, 8) k_level_td(GView g, WView w, KParams kp) {
-  level_body(g, w, kp, kDirTD);
+  level_body<kBlock>(g, w, kp, kDirTD);
 }
 
-__global__ void __launch_bounds__(kBlock, 8) k_level_bu(GView g, WView w, KParams kp) {
-  level_body(g, w, kp, kDirBU);
+/* Larger workgroups at the same occupancy (two per CU): each keeps a
+   larger part of the frontier bitmap in LDS. */
+__global__ void __launch_bounds__(kBuBlock, 8) k_level_bu(GView g, WView w, KParams kp) {
+  level_body<kBuBlock>(g, w, kp, kDirBU);
 }
 
 /* Exclusive prefix sum over the workgroup; *total gets the sum. */
@@ -800,10 +803,10 @@ hipError_t level_grid(int* grid) {
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_level_bu), kBlock, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_level_bu), kBuBlock, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
-  *grid = cus * per_cu;
+  *grid = cus * per_cu * (kBuBlock / kBlock);  /* in kBlock-thread workgroups */
   return hipSuccess;
 }
 
@@ -823,7 +826,8 @@ hipError_t launch_level(const GView& g, const WView& w, const KParams& kp, int g
   /* a top-down level that ends by deciding bottom-up lets the next level
      run in the same slot */
   hipLaunchKernelGGL(k_level_td, dim3(grid), dim3(kBlock), 0, s, g, w, kp);
-  hipLaunchKernelGGL(k_level_bu, dim3(grid), dim3(kBlock), 0, s, g, w, kp);
+  hipLaunchKernelGGL(k_level_bu, dim3((grid + kBuBlock / kBlock - 1) / (kBuBlock / kBlock)), dim3(kBuBlock), 0, s,
+                     g, w, kp);
   return hipGetLastError();
 }
 

@@ -56,9 +56,10 @@ __device__ __forceinline__ T ld_agent(const T* p) {
    (one cache line each) and the last of each group forwards the group's sums
    to the level counters, so no address sees more than gridDim/kGroups
    atomics. */
+template <int BT = kBlock>
 __device__ bool finish_block(Ctl* c, Acc a, uint32_t nblocks = 0) {
-  __shared__ int64_t part[4][kBlock / kWave];
-  __shared__ unsigned long long bpart[kBlock / kWave];
+  __shared__ int64_t part[4][BT / kWave];
+  __shared__ unsigned long long bpart[BT / kWave];
   __shared__ int is_last;
   const int lane = lane_id(), wv = threadIdx.x / kWave;
   for (int o = 32; o > 0; o >>= 1) a.bits |= __shfl_xor(a.bits, o);
@@ -78,8 +79,8 @@ __device__ bool finish_block(Ctl* c, Acc a, uint32_t nblocks = 0) {
     int64_t sum[4] = {0, 0, 0, 0};
     unsigned long long bits = 0ull;
     for (int k = 0; k < 4; ++k)
-      for (int j = 0; j < kBlock / kWave; ++j) sum[k] += part[k][j];
-    for (int j = 0; j < kBlock / kWave; ++j) bits |= bpart[j];
+      for (int j = 0; j < BT / kWave; ++j) sum[k] += part[k][j];
+    for (int j = 0; j < BT / kWave; ++j) bits |= bpart[j];
     const uint32_t nb = nblocks ? nblocks : gridDim.x; /* workgroups taking part */
     if (nb == 1) { /* alone: no other workgroup to wait for or to race with */
       c->nf_next += sum[0];

@@ -52,7 +52,8 @@ constexpr int kMsTake = 256;         /* batched push: entries per row and round 
 
 constexpr int kGroups = 64;
 constexpr int kBuWords = 4;          /* 64-vertex words a bottom-up wavefront takes at a time */
-constexpr int kBuHot32 = 4096;       /* 32-bit frontier words a bottom-up workgroup keeps in LDS (16 KB) */
+constexpr int kBuBlock = 1024;       /* threads per bottom-up workgroup (two per CU) */
+constexpr int kBuHot32 = 16384;      /* 32-bit frontier words a bottom-up workgroup keeps in LDS (64 KB) */
 constexpr int kDirectCap = 1 << 16;  /* entries of a direct queue; a top-down level whose
                                         frontier has at most this many edges appends its
                                         claims to the next level's queue itself */
