@@ -567,7 +567,7 @@ __device__ int64_t block_excl_scan(int64_t x, int64_t* total) {
 
 /* Expands the split top-down vertices (kAuxHuge) or turns the frontier
    bitmap of a level about to run top-down into its queue (kAuxToQueue). */
-__global__ void __launch_bounds__(kBlock) k_aux(GView g, WView w, KParams kp) {
+__global__ void __launch_bounds__(kBlock, 8) k_aux(GView g, WView w, KParams kp) {
   Ctl* c = w.ctl;
   if (c->done) return;
   const int aux = c->aux;
@@ -603,9 +603,52 @@ __global__ void __launch_bounds__(kBlock) k_aux(GView g, WView w, KParams kp) {
       const int64_t rb = g.off[u], re = g.off[u + 1];
       const int64_t beg = rb + (ch - (int64_t)w.huge_base[lo]) * kHugeChunk;
       const int64_t end = min(re, beg + (int64_t)kHugeChunk);
-      for (int64_t k = beg + lane; k < end; k += kWave) {
-        const int32_t v = g.idx[k];
-        if (try_claim(w.vis, v)) claimed(g, w, f_nxt, q_app, v, u, uc, L, a);
+      /* A lane's entries of the chunk go through each step J at a time
+         (neighbour IDs, visited words, claims, then the winners' labels
+         and degrees), so a lane has J independent accesses in flight per
+         step instead of walking dependent chains one after another.  Lanes
+         without an entry use index 0 (in bounds) and are masked. */
+      constexpr int J = kHugeBatch;
+      uint32_t* vis32 = reinterpret_cast<uint32_t*>(w.vis);
+      const uint32_t* off_lo = reinterpret_cast<const uint32_t*>(g.off);
+      for (int64_t k0 = beg + lane; k0 < end; k0 += (int64_t)J * kWave) {
+        int32_t v[J];
+        uint32_t vw[J], old[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const int64_t k = k0 + (int64_t)j * kWave;
+          v[j] = g.idx[k < end ? k : beg];
+          if (k >= end) v[j] = -1;
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) vw[j] = vis32[v[j] >= 0 ? (uint32_t)v[j] >> 5 : 0u];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          old[j] = ~0u;
+          const uint32_t bit = 1u << (v[j] & 31);
+          if (v[j] >= 0 && !(vw[j] & bit)) old[j] = atomicOr(vis32 + ((uint32_t)v[j] >> 5), bit);
+        }
+        uint32_t won = 0u;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+          if (!(old[j] & (1u << (v[j] & 31)))) won |= 1u << j;
+        uint32_t ob[J], oe[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const uint32_t x = ((won >> j) & 1u) ? (uint32_t)v[j] : 0u;
+          ob[j] = off_lo[2 * (uint64_t)x];
+          oe[j] = off_lo[2 * (uint64_t)x + 2];
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          if ((won >> j) & 1u) {
+            store_labels(w, v[j], L + 1, u, uc);
+            atomicOr(reinterpret_cast<uint32_t*>(f_nxt) + ((uint32_t)v[j] >> 5), 1u << (v[j] & 31));
+            if (q_app) q_app[atomicAdd(&w.ctl->qd_fill, 1ull)] = v[j];
+            a.found += 1;
+            a.found_deg += (int32_t)(oe[j] - ob[j]);  /* degrees fit in 31 bits */
+          }
+        }
       }
     }
     if (finish_block(c, a)) {
