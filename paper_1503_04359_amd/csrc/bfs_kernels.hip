@@ -165,6 +165,49 @@ __device__ __forceinline__ void claimed(const GView& g, const WView& w, uint64_t
   a.found_deg += g.off[v + 1] - g.off[v];
 }
 
+/* Claims for J neighbour IDs of one lane (v[j] < 0: none), all from
+   frontier vertex u (caller ID uc): each step (visited words, claim
+   atomics, the winners' row bounds) is issued for all J before any result
+   is used, so a lane has J independent accesses in flight instead of J
+   dependent chains in a row.  Lanes with nothing to load read index 0 (in
+   bounds) and are masked. */
+template <int J>
+__device__ __forceinline__ void claim_batch(const GView& g, const WView& w, uint64_t* f_nxt, int32_t* q_app,
+                                            const int32_t (&v)[J], int32_t u, int32_t uc, int32_t L, Acc& a) {
+  uint32_t* vis32 = reinterpret_cast<uint32_t*>(w.vis);
+  const uint32_t* off_lo = reinterpret_cast<const uint32_t*>(g.off);
+  uint32_t vw[J], old[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) vw[j] = vis32[v[j] >= 0 ? (uint32_t)v[j] >> 5 : 0u];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    old[j] = ~0u;
+    const uint32_t bit = 1u << (v[j] & 31);
+    if (v[j] >= 0 && !(vw[j] & bit)) old[j] = atomicOr(vis32 + ((uint32_t)v[j] >> 5), bit);
+  }
+  uint32_t won = 0u;
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+    if (!(old[j] & (1u << (v[j] & 31)))) won |= 1u << j;
+  uint32_t ob[J], oe[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const uint32_t x = ((won >> j) & 1u) ? (uint32_t)v[j] : 0u;
+    ob[j] = off_lo[2 * (uint64_t)x];
+    oe[j] = off_lo[2 * (uint64_t)x + 2];
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if ((won >> j) & 1u) {
+      store_labels(w, v[j], L + 1, u, uc);
+      atomicOr(reinterpret_cast<uint32_t*>(f_nxt) + ((uint32_t)v[j] >> 5), 1u << (v[j] & 31));
+      if (q_app) q_app[atomicAdd(&w.ctl->qd_fill, 1ull)] = v[j];
+      a.found += 1;
+      a.found_deg += (int32_t)(oe[j] - ob[j]);  /* degrees fit in 31 bits */
+    }
+  }
+}
+
 __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int32_t L, uint32_t nblocks, Acc& a) {
   Ctl* c = w.ctl;
   /* control fields may have been written by this workgroup's own previous
@@ -200,9 +243,15 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
 
     /* lane per vertex */
     const int64_t sdeg = (valid && !huge && !med) ? deg : 0;
-    for (int64_t j = 0; j < sdeg; ++j) {
-      const int32_t v = g.idx[beg + j];
-      if (try_claim(w.vis, v)) claimed(g, w, f_nxt, q_app, v, u, uc, L, a);
+    constexpr int JS = 2;  /* two at a time: the kernel's register budget allows no more */
+    for (int64_t j0 = 0; j0 < sdeg; j0 += JS) {
+      int32_t v[JS];
+#pragma unroll
+      for (int j = 0; j < JS; ++j) {
+        v[j] = g.idx[beg + min(j0 + j, sdeg - 1)];  /* in the row */
+        if (j0 + j >= sdeg) v[j] = -1;
+      }
+      claim_batch<JS>(g, w, f_nxt, q_app, v, u, uc, L, a);
     }
 
     /* wavefront per vertex */
@@ -610,46 +659,15 @@ __global__ void __launch_bounds__(kBlock, 8) k_aux(GView g, WView w, KParams kp)
          step instead of walking dependent chains one after another.  Lanes
          without an entry use index 0 (in bounds) and are masked. */
       constexpr int J = kHugeBatch;
-      uint32_t* vis32 = reinterpret_cast<uint32_t*>(w.vis);
-      const uint32_t* off_lo = reinterpret_cast<const uint32_t*>(g.off);
       for (int64_t k0 = beg + lane; k0 < end; k0 += (int64_t)J * kWave) {
         int32_t v[J];
-        uint32_t vw[J], old[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
           const int64_t k = k0 + (int64_t)j * kWave;
           v[j] = g.idx[k < end ? k : beg];
           if (k >= end) v[j] = -1;
         }
-#pragma unroll
-        for (int j = 0; j < J; ++j) vw[j] = vis32[v[j] >= 0 ? (uint32_t)v[j] >> 5 : 0u];
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-          old[j] = ~0u;
-          const uint32_t bit = 1u << (v[j] & 31);
-          if (v[j] >= 0 && !(vw[j] & bit)) old[j] = atomicOr(vis32 + ((uint32_t)v[j] >> 5), bit);
-        }
-        uint32_t won = 0u;
-#pragma unroll
-        for (int j = 0; j < J; ++j)
-          if (!(old[j] & (1u << (v[j] & 31)))) won |= 1u << j;
-        uint32_t ob[J], oe[J];
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-          const uint32_t x = ((won >> j) & 1u) ? (uint32_t)v[j] : 0u;
-          ob[j] = off_lo[2 * (uint64_t)x];
-          oe[j] = off_lo[2 * (uint64_t)x + 2];
-        }
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-          if ((won >> j) & 1u) {
-            store_labels(w, v[j], L + 1, u, uc);
-            atomicOr(reinterpret_cast<uint32_t*>(f_nxt) + ((uint32_t)v[j] >> 5), 1u << (v[j] & 31));
-            if (q_app) q_app[atomicAdd(&w.ctl->qd_fill, 1ull)] = v[j];
-            a.found += 1;
-            a.found_deg += (int32_t)(oe[j] - ob[j]);  /* degrees fit in 31 bits */
-          }
-        }
+        claim_batch<J>(g, w, f_nxt, q_app, v, u, uc, L, a);
       }
     }
     if (finish_block(c, a)) {
