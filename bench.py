@@ -70,12 +70,17 @@ def level_bytes(rec: dict, words_active: int) -> float:
 
 def kernel_source_digest() -> str:
     """Identity of the level kernel's source: measured traffic is only
-    reported for the kernel it was measured on."""
+    reported for the kernel it was measured on.  Comments and blank space
+    are left out, so that editing a comment does not void a measurement."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("bfs_kernels.hip", "device_common.h", "dobfs_internal.h"):
-        with open(os.path.join(ROOT, "paper_1503_04359_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1503_04359_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)  # block comments
+        text = re.sub(r"//[^\n]*", " ", text)                # line comments
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

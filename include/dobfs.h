@@ -101,8 +101,8 @@ typedef struct {
   int32_t td_huge_cut;     /* top-down: degree above which a vertex's edges
                               are split over many wavefronts (default 256,
                               at least 64)                                  */
-  int32_t bu_heavy_cut;    /* bottom-up: degree above which a wavefront scans
-                              one vertex cooperatively (default 256)        */
+  int32_t bu_heavy_cut;    /* bottom-up: most neighbours one vertex tests per
+                              search round, at least 64 (default 256)       */
   int32_t chunk_levels;    /* levels enqueued per host check (default 8)    */
   uint32_t flags;          /* DOBFS_RUN_* (default 0)                       */
   int32_t kappa_x1000;     /* COST, default 500                             */

@@ -14,26 +14,29 @@
  * (Section 3.3) to on-device counters, so no level needs the host.
  *
  * Mapping to the hardware:
- *   - bottom-up: one wavefront per 64-vertex visited word; lane i owns
- *     vertex 64w+i.  Fully visited words are skipped wave-uniformly, the new
- *     frontier word is the wave's ballot and visited |= ballot is one plain
- *     store: bottom-up needs no atomics.  Vertices above bu_heavy_cut are
- *     scanned 64 neighbours at a time by the whole wave, stopping at the
- *     first hit.
- *   - bottom-up work inside a word is balanced across lanes: adjacency
- *     lists are consumed in rounds of growing per-vertex quotas laid end to
- *     end over the 64 lanes (see bottom_up).
+ *   - bottom-up: lane i of a wavefront owns vertex 64w+i of each 64-vertex
+ *     visited word w it takes.  Fully visited words are skipped
+ *     wave-uniformly, the new frontier word is the wave's ballot and
+ *     visited |= ballot is one plain store: bottom-up needs no atomics.
+ *     Round 0 (each vertex's first neighbour) runs for four words at a time
+ *     with all their loads in flight together; the vertices that miss are
+ *     searched in a second pass over the same words, in rounds of growing
+ *     per-vertex quotas (at most max(64, bu_heavy_cut) per round) laid end
+ *     to end over the 64 lanes, so work inside a word is balanced across
+ *     lanes (see bottom_up).  Probes of the hub region of the frontier read
+ *     an LDS copy.
  *   - top-down: degree-binned (the virtual-warp idea of Section 2.1 on
  *     64-wide wavefronts): a lane per vertex up to td_wave_cut, a wavefront
  *     per vertex up to td_huge_cut, and above that the vertex's edges are
  *     cut into kHugeChunk-edge tasks spread over all wavefronts by the aux
  *     kernel.
- *   - frontier representations: every level produces the next frontier as
- *     a bitmap only (top-down sets bits with atomic OR, bottom-up writes
- *     whole words).  Before a top-down level the aux kernel turns that
+ *   - frontier representations: a level produces the next frontier as a
+ *     bitmap (top-down sets bits with atomic OR, bottom-up writes whole
+ *     words).  Before a large top-down level the aux kernel turns that
  *     bitmap into a queue with one atomic per workgroup, and clears the
- *     other bitmap buffer, which the top-down level then fills.  Bitmap
- *     buffer F[L%2] holds F_L.
+ *     other bitmap buffer, which the top-down level then fills.  A small
+ *     top-down level also appends its claims to a direct queue that the
+ *     next top-down level reads as is.  Bitmap buffer F[L%2] holds F_L.
  */
 #include <hip/hip_runtime.h>
 
