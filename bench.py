@@ -494,8 +494,8 @@ def main() -> int:
         return 0
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the single-GPU result is the throughput of one GPU).", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the traversal is not sharded across GPUs; the result is one GPU's throughput).", file=sys.stderr)
         return 2
 
     import __graft_entry__

@@ -1,0 +1,73 @@
+"""bench.py's host-side pieces (no GPU): the one-GPU guard, the traffic
+figure computed from counter files, and the source digest that ties a
+traffic figure to the kernel it was measured on."""
+from __future__ import annotations
+
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+HEADER = ('"Correlation_Id","Dispatch_Id","Agent_Id","Queue_Id","Process_Id","Thread_Id","Grid_Size",'
+          '"Kernel_Id","Kernel_Name","Workgroup_Size","LDS_Block_Size","Scratch_Size","VGPR_Count",'
+          '"Accum_VGPR_Count","SGPR_Count","Counter_Name","Counter_Value","Start_Timestamp","End_Timestamp"\n')
+
+
+def _csv(path, counter, rows):
+    with open(path, "w") as f:
+        f.write(HEADER)
+        for i, (name, kib) in enumerate(rows):
+            f.write(f'{i},{i},"Agent 1",1,1,1,256,1,"{name}",256,0,0,8,0,16,"{counter}",{kib},0,1\n')
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_traffic_from_counters(tmp_path):
+    probe = "void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add<int>>(int)"
+    td = "dobfs::(anonymous namespace)::k_level_td(dobfs::GView, dobfs::WView, dobfs::KParams)"
+    bu = "dobfs::(anonymous namespace)::k_level_bu(dobfs::GView, dobfs::WView, dobfs::KParams)"
+    other = "dobfs::(anonymous namespace)::k_finalize(dobfs::GView, dobfs::WView, int)"
+    # a 1 MiB probe reads as 512 KiB fetched and 1024 KiB written: factors 2 and 1
+    _csv(tmp_path / "f.csv", "FETCH_SIZE", [(probe, 512.0), (td, 10.0), (bu, 30.0), (other, 999.0), (td, 0.0),
+                                            (bu, 20.0)])
+    _csv(tmp_path / "w.csv", "WRITE_SIZE", [(probe, 1024.0), (td, 4.0), (bu, 6.0), (td, 0.0), (bu, 10.0)])
+    out = tmp_path / "traffic.json"
+    ent = bench.traffic_from_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 1 << 20, "k", str(out))
+    assert ent["launches"] == 2
+    assert ent["fetch_factor"] == pytest.approx(2.0) and ent["write_factor"] == pytest.approx(1.0)
+    assert ent["fetch_bytes_per_launch"] == round(60 * 1024 * 2 / 2)
+    assert ent["write_bytes_per_launch"] == round(20 * 1024 / 2)
+    assert ent["bytes_per_launch"] == ent["fetch_bytes_per_launch"] + ent["write_bytes_per_launch"]
+    assert json.loads(out.read_text())["k"]["source_sha256"] == bench.kernel_source_digest()
+
+
+def test_source_digest_ignores_comments_only(tmp_path, monkeypatch):
+    src = os.path.join(ROOT, "paper_1503_04359_amd", "csrc")
+    dst = tmp_path / "paper_1503_04359_amd" / "csrc"
+    dst.mkdir(parents=True)
+    for f in ("bfs_kernels.hip", "device_common.h", "dobfs_internal.h"):
+        shutil.copy(os.path.join(src, f), dst / f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    base = bench.kernel_source_digest()
+    p = dst / "dobfs_internal.h"
+    p.write_text(p.read_text() + "\n/* a new comment */\n// and another\n")
+    assert bench.kernel_source_digest() == base
+    p.write_text(p.read_text() + "\nconstexpr int kUnused = 1;\n")
+    assert bench.kernel_source_digest() != base
+
+
+def test_harmonic_mean():
+    assert bench.harmonic_mean([1.0, 1.0]) == pytest.approx(1.0)
+    assert bench.harmonic_mean([1.0, 3.0]) == pytest.approx(1.5)
