@@ -620,7 +620,9 @@ __device__ int64_t block_excl_scan(int64_t x, int64_t* total) {
 
 /* Expands the split top-down vertices (kAuxHuge) or turns the frontier
    bitmap of a level about to run top-down into its queue (kAuxToQueue). */
-__global__ void __launch_bounds__(kBlock, 8) k_aux(GView g, WView w, KParams kp) {
+/* Not held to 8 waves per SIMD: claiming eight split-row entries per lane at
+   a time needs more registers than that allows, and measured faster at 7. */
+__global__ void __launch_bounds__(kBlock) k_aux(GView g, WView w, KParams kp) {
   Ctl* c = w.ctl;
   if (c->done) return;
   const int aux = c->aux;

@@ -37,7 +37,7 @@ namespace dobfs {
 constexpr int kBlock = 256;          /* threads per workgroup (4 wavefronts) */
 constexpr int kWave = 64;
 constexpr int kHugeChunk = 512;      /* edges per wavefront task for split vertices */
-constexpr int kHugeBatch = 4;        /* a split task's entries a lane claims at a time */
+constexpr int kHugeBatch = 8;        /* a split task's entries a lane claims at a time */
 constexpr int kMinHugeCut = 64;      /* lower bound of td_huge_cut */
 constexpr int kDirTD = 0;
 constexpr int kDirBU = 1;
