@@ -85,8 +85,8 @@ enum {
 /* Checks, for the traversal from `root`:
      root:      depth[root] = 0, parent[root] = root;
      unreached: depth[v] = -1 exactly when parent[v] = -1;
-     tree:      for reached v != root, (parent[v], v) is an edge and
-                depth[parent[v]] = depth[v] - 1;
+     tree:      for every reached v != root (depth 0 included), (parent[v], v)
+                is an edge and depth[parent[v]] = depth[v] - 1, so depth[v] >= 1;
      edges:     for every edge (u, v) both ends are reached or both are not,
                 and |depth[u] - depth[v]| <= 1.
    The tree property bounds each depth from above by the hop distance's walk
@@ -114,11 +114,13 @@ int oracle_check_tree(int64_t n, const int64_t* off, const int32_t* idx, int64_t
     } else if ((dv == -1) != (pv == -1)) {
       code = CHECK_UNREACHED;
     } else {
-      if (dv > 0) {
+      if (dv >= 0 && v != root) {
+        /* I2 holds for every reached vertex other than the root; a second
+           vertex of depth 0 has no parent one level up. */
         int found = 0;
         for (int64_t e = off[v]; e < off[v + 1] && !found; ++e) found = (idx[e] == pv);
         if (!found) code = CHECK_PARENT_NOT_EDGE;
-        else if (depth[pv] != dv - 1) code = CHECK_PARENT_DEPTH;
+        else if (dv == 0 || depth[pv] != dv - 1) code = CHECK_PARENT_DEPTH;
       }
       for (int64_t e = off[v]; e < off[v + 1] && code == CHECK_OK; ++e) {
         const int32_t du = depth[idx[e]];
@@ -136,11 +138,11 @@ int oracle_check_tree(int64_t n, const int64_t* off, const int32_t* idx, int64_t
     if (dv < -1 || pv < -1 || (int64_t)pv >= n) first_code = CHECK_RANGE;
     else if ((dv == -1) != (pv == -1)) first_code = CHECK_UNREACHED;
     else {
-      if (dv > 0) {
+      if (dv >= 0 && v != root) {
         int found = 0;
         for (int64_t e = off[v]; e < off[v + 1] && !found; ++e) found = (idx[e] == pv);
         if (!found) first_code = CHECK_PARENT_NOT_EDGE;
-        else if (depth[pv] != dv - 1) first_code = CHECK_PARENT_DEPTH;
+        else if (dv == 0 || depth[pv] != dv - 1) first_code = CHECK_PARENT_DEPTH;
       }
       if (first_code == CHECK_OK) first_code = CHECK_EDGE_SPAN;
     }

@@ -290,6 +290,51 @@ def test_checker_rejects_planted_faults(kron11):
     assert _code(g, r, d, p6) == (2, v)
 
 
+def test_checker_rejects_second_depth_zero_vertex():
+    # I2 applies to every reached vertex other than the root, depth 0
+    # included.  On path(3) from 0, labelling vertex 1 as a second root
+    # (depth 0, its own parent) keeps every edge span <= 1.
+    g = gg.path(3)
+    d = np.array([0, 0, 1], dtype=np.int32)
+    p = np.array([0, 1, 1], dtype=np.int32)
+    assert oracle.check_tree(g.offsets, g.indices, 0, d, p) == (4, 1)
+    # The same vertex given a real neighbour as parent: the parent-depth
+    # test must still fail, since no vertex has depth -1 + 1 = 0 but the root.
+    p = np.array([0, 0, 1], dtype=np.int32)
+    assert oracle.check_tree(g.offsets, g.indices, 0, d, p) == (5, 1)
+    # A subtree hung one level too shallow under that vertex: path(4).
+    g = gg.path(4)
+    d = np.array([0, 0, 1, 2], dtype=np.int32)
+    p = np.array([0, 0, 1, 2], dtype=np.int32)
+    assert oracle.check_tree(g.offsets, g.indices, 0, d, p) == (5, 1)
+
+
+def test_checker_rejects_shallow_subtree_kronecker(kron11):
+    # Kronecker scale 11: a depth-1 vertex v relabelled as depth 0 and its
+    # whole BFS subtree (by the oracle's parents) moved one level up.
+    g, r, d, p = kron11
+    ones = np.flatnonzero(d == 1)
+    children = {}
+    for x in range(g.n):
+        if d[x] > 0:
+            children.setdefault(int(p[x]), []).append(x)
+    v = max(ones.tolist(), key=lambda x: len(children.get(int(x), [])))
+    d2 = d.copy()
+    stack = [int(v)]
+    while stack:
+        x = stack.pop()
+        d2[x] -= 1
+        stack.extend(children.get(x, []))
+    code, bad = oracle.check_tree(g.offsets, g.indices, r, d2, p)
+    assert code != 0
+    # and the fake root alone, with the rest of its subtree untouched
+    d3 = d.copy(); d3[v] = 0
+    code, bad = oracle.check_tree(g.offsets, g.indices, r, d3, p)
+    assert code != 0
+    if bad == v:
+        assert code == 5
+
+
 def test_checker_rejects_dfs_tree_on_cycle():
     # A depth-first tree satisfies the parent properties but not the edge
     # span: depth i along the cycle from 0.
