@@ -22,6 +22,20 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it first (python __graft_entry__.py build, "
         "or python paper_1503_04359_amd/_build.py)")
 
+
+def _check_stamp() -> None:
+    """Refuses a library built from sources other than the ones in the tree
+    (its stamp holds their digest; see _build.py)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("_dobfs_build", os.path.join(_HERE, "_build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    if not mod.is_current():
+        raise ImportError(f"{LIB_PATH} is older than its sources: rebuild it (python __graft_entry__.py build)")
+
+
+_check_stamp()
+
 # torch first: it brings the process's HIP runtime, which the library then
 # shares; loading the library first would start a second runtime that sees
 # no device once torch's is up.

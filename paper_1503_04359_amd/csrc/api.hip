@@ -103,9 +103,13 @@ struct dobfs_graph_s {
   int32_t* idx = nullptr;
   uint64_t* iso = nullptr;
   int32_t* first = nullptr;    /* first neighbour of each vertex, -1 if none */
-  int32_t* first_caller = nullptr; /* relabelled graphs: its caller ID, built by the
-                                       first run (the caller may free the source
-                                       CSR after upload), skipped if memory is short */
+  /* Relabelled graphs: the caller ID of first[v], built by the first run
+     (the caller may free its source CSR after upload, which makes room),
+     skipped if memory is short.  Published only once filled: a run reads
+     the pointer with acquire order, and the build sets first_caller_tried
+     with release order after the column is complete (or given up), both
+     under `mu`. */
+  std::atomic<int32_t*> first_caller{nullptr};
   std::atomic<bool> first_caller_tried{false};
   int32_t* new2old = nullptr;  /* relabelled graphs only */
   int32_t* old2new = nullptr;
@@ -124,7 +128,7 @@ struct dobfs_graph_s {
     g.idx = idx;
     g.iso = iso;
     g.first = first;
-    g.first_caller = first_caller;
+    g.first_caller = first_caller.load(std::memory_order_acquire);
     g.old2new = old2new;
     g.new2old = new2old;
     g.seg_lo = seg_lo;
@@ -222,6 +226,22 @@ void release_workspace(dobfs_graph_s* g, Workspace* w) {
   std::lock_guard<std::mutex> lk(g->mu);
   w->busy = false;
 }
+
+/* Returns a run's workspace to the pool on every exit path.  Once anything
+   has been enqueued (`launched`), an early return still marks the end of
+   the stream's work with the idle event, so the workspace is not handed to
+   another run while kernels of this one may still use it; if even that
+   record fails, the stream is drained first. */
+struct RunGuard {
+  dobfs_graph_s* g;
+  Workspace* w;
+  hipStream_t s;
+  bool launched = false;
+  ~RunGuard() {
+    if (launched && hipEventRecord(w->idle, s) != hipSuccess) (void)hipStreamSynchronize(s);
+    release_workspace(g, w);
+  }
+};
 
 KParams to_kparams(const dobfs_params& p) {
   KParams k;
@@ -410,7 +430,7 @@ int dobfs_graph_upload(const int64_t* offsets, const int32_t* indices, int64_t n
       }
       dfree(g->iso);
       dfree(g->first);
-      dfree(g->first_caller);
+      dfree(g->first_caller.load());
       dfree(g->new2old);
       dfree(g->old2new);
       dfree(g->seg_lo);
@@ -523,7 +543,7 @@ int dobfs_graph_free(dobfs_graph_t g) {
   }
   dfree(g->iso);
   dfree(g->first);
-  dfree(g->first_caller);
+  dfree(g->first_caller.load());
   dfree(g->new2old);
   dfree(g->old2new);
   dfree(g->seg_lo);
@@ -540,7 +560,7 @@ int dobfs_graph_info(dobfs_graph_t g, dobfs_graph_info_t* info) {
   info->max_degree = g->max_degree;
   info->device_bytes = (g->owns_csr ? (int64_t)sizeof(int64_t) * (g->n + 1) + (int64_t)sizeof(int32_t) * g->m : 0) +
                        (int64_t)sizeof(uint64_t) * g->words + 4 * g->n + (g->new2old ? 8 * g->n : 0) +
-                       (g->first_caller ? 4 * g->n : 0);
+                       (g->first_caller.load() ? 4 * g->n : 0);
   info->flags = g->flags;
   return DOBFS_OK;
 }
@@ -564,27 +584,27 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
   if (st != DOBFS_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Workspace* w = nullptr;
-  if (g->new2old && !g->first_caller_tried) {
+  if (g->new2old && !g->first_caller_tried.load(std::memory_order_acquire)) {
     std::lock_guard<std::mutex> lk(g->mu);
-    if (!g->first_caller_tried) {
-      g->first_caller_tried = true;
-      hipError_t e2 = dalloc(&g->first_caller, g->n);
+    if (!g->first_caller_tried.load(std::memory_order_relaxed)) {
+      int32_t* col = nullptr;
+      hipError_t e2 = dalloc(&col, g->n);
       if (e2 == hipSuccess) {
-        e2 = launch_first_caller(g->first, g->new2old, g->n, g->first_caller, g->grid, s);
+        e2 = launch_first_caller(g->first, g->new2old, g->n, col, g->grid, s);
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
-        if (e2 != hipSuccess) return fail(DOBFS_EDEVICE, "first-neighbour caller column", e2);
+        if (e2 != hipSuccess) {
+          dfree(col); /* not published; a later run tries again */
+          return fail(DOBFS_EDEVICE, "first-neighbour caller column", e2);
+        }
+        g->first_caller.store(col, std::memory_order_release);
       } else {
-        g->first_caller = nullptr; /* optional: parents are then all mapped by the finalize kernel */
-        (void)hipGetLastError();
+        (void)hipGetLastError(); /* optional: parents are then all mapped by the finalize kernel */
       }
+      g->first_caller_tried.store(true, std::memory_order_release);
     }
   }
   if ((st = acquire_workspace(g, &w)) != DOBFS_OK) return st;
-  struct Guard {
-    dobfs_graph_s* g;
-    Workspace* w;
-    ~Guard() { release_workspace(g, w); }
-  } guard{g, w};
+  RunGuard guard{g, w, s};
   if (!parent && !g->new2old) {
     if (!w->parent_scratch) {
       hipError_t e = dalloc(&w->parent_scratch, g->n);
@@ -627,6 +647,7 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
     DOBFS_HIP(hipStreamSynchronize(s), "roots copy");
     roots_dev = w->roots_dev;
   }
+  guard.launched = true;
   DOBFS_HIP(launch_init(gv, wv, roots_dev, roots ? nroots : 1, root, first_direction(prm), g->grid, s),
             "init launch");
   const bool timed = (prm.flags & DOBFS_RUN_TIME_KERNELS) != 0;
@@ -651,6 +672,7 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
     if (roots) DOBFS_HIP(launch_fix_roots(wv, roots_dev, nroots, s), "root labels launch");
   }
   DOBFS_HIP(hipEventRecord(w->idle, s), "idle event");
+  guard.launched = false;
   if (!stats) return DOBFS_OK;
   std::vector<float> kms;
   if (timed) {
@@ -692,11 +714,7 @@ int dobfs_batch_submit(dobfs_graph_t g, const int64_t* roots, int32_t k, int32_t
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Workspace* w = nullptr;
   if ((st = acquire_workspace(g, &w)) != DOBFS_OK) return st;
-  struct Guard {
-    dobfs_graph_s* g;
-    Workspace* w;
-    ~Guard() { release_workspace(g, w); }
-  } guard{g, w};
+  RunGuard guard{g, w, s};
   if ((st = ensure_ms_buffers(g, w, k)) != DOBFS_OK) return st;
   const GView gv = g->view();
   MsView m;
@@ -718,6 +736,7 @@ int dobfs_batch_submit(dobfs_graph_t g, const int64_t* roots, int32_t k, int32_t
   m.split_u = w->huge_u;
   m.split_base = w->huge_base;
   const KParams kp = to_kparams(prm);
+  guard.launched = true;
   DOBFS_HIP(launch_ms_init(gv, m, r, first_direction(prm) == kDirBU ? 1 : 0, g->grid, s), "batch init launch");
   auto level = [&](int64_t) -> int {
     DOBFS_HIP(launch_ms_level(gv, m, kp, g->grid, s), "batch level launch");
@@ -727,6 +746,7 @@ int dobfs_batch_submit(dobfs_graph_t g, const int64_t* roots, int32_t k, int32_t
   if ((st = level_loop(w, w->ctl, prm.chunk_levels, g->n + 1, s, level, &launches)) != DOBFS_OK) return st;
   if (g->new2old) DOBFS_HIP(launch_ms_finalize(gv, m, r, g->grid, s), "batch finalize launch");
   DOBFS_HIP(hipEventRecord(w->idle, s), "idle event");
+  guard.launched = false;
   if (!stats) return DOBFS_OK;
   return fill_stats(w, s, stats, launches, std::vector<float>());
 }

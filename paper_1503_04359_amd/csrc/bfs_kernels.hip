@@ -211,7 +211,10 @@ __device__ __forceinline__ void claim_batch(const GView& g, const WView& w, uint
   }
 }
 
-__device__ void top_down(const GView& g, const WView& w, const KParams& kp, int32_t L, uint32_t nblocks, Acc& a) {
+/* Top-down level L, as workgroup vb of the nblocks workgroups that share its
+   queue. */
+__device__ void top_down(const GView& g, const WView& w, const KParams& kp, int32_t L, uint32_t vb, uint32_t nblocks,
+                         Acc& a) {
   Ctl* c = w.ctl;
   /* control fields may have been written by this workgroup's own previous
      level (see level_body): read them from L2 */
@@ -224,7 +227,7 @@ __device__ void top_down(const GView& g, const WView& w, const KParams& kp, int3
   const bool append = ld_agent(&c->q_append) != 0;
   int32_t* q_app = append ? ((L & 1) ? w.qd0 : w.qd1) : nullptr;
   const int lane = lane_id();
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t wave = ((int64_t)vb * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)nblocks * blockDim.x) / kWave;
   const int64_t wave_cut = kp.td_wave_cut, huge_cut = kp.td_huge_cut;
 
@@ -547,43 +550,58 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
 
 /* The level kernels: top-down and bottom-up are separate kernels, both
    launched for every level, so that each gets its own register allocation;
-   the one whose direction is not the level's returns at once. */
+   the one whose direction is not the level's returns at once.
+
+   Completion protocol.  Every workgroup of the grid that finds the level in
+   its direction reports to the completion count, also a top-down workgroup
+   with no queue entries of its own (a top-down level needs only one queue
+   entry per thread, i.e. ceil(n_f / kBlock) workgroups, and the others
+   report empty counters).  The control state therefore cannot change
+   before every workgroup of the launch has read it: a workgroup dispatched
+   late, when other kernels hold the compute units, still sees the level
+   the launch was enqueued for, and no ticket is left over for a later
+   launch.
+
+   The workgroup that closes a top-down level goes straight on to the next
+   one when that level is again top-down, has its queue handed on directly
+   and fits one workgroup: it runs it alone, as workgroup 0 of a
+   one-workgroup level, since every other workgroup of the launch has
+   already reported and left.  Long chains of tiny levels (path-like tails)
+   cost a barrier each instead of a launch sequence each. */
 template <int BT>
 __device__ __forceinline__ void level_body(const GView& g, const WView& w, const KParams& kp, int32_t want_dir) {
   Ctl* c = w.ctl;
-  /* A top-down level needs only enough workgroups for one queue entry per
-     thread; the others leave before the completion count.  When that is a
-     single workgroup and the next level is again a small top-down level
-     with its queue handed on directly, the workgroup goes straight on to
-     it: long chains of tiny levels (path-like tails) cost a barrier each
-     instead of a launch sequence each. */
-  for (;;) {
-    if (ld_agent(&c->done) || ld_agent(&c->aux) != kAuxNone || ld_agent(&c->dir) != want_dir) return;
+  if (ld_agent(&c->done) || ld_agent(&c->aux) != kAuxNone || ld_agent(&c->dir) != want_dir) return;
+  for (bool alone = false;; alone = true) {
     const int32_t L = ld_agent(&c->level);
-    uint32_t nb = gridDim.x;
+    const uint32_t vb = alone ? 0u : blockIdx.x;
+    uint32_t nb = alone ? 1u : gridDim.x;
     if (want_dir == kDirTD) {
       const int64_t need = (ld_agent(&c->n_f) + kBlock - 1) / kBlock;
       if (need < (int64_t)nb) nb = need < 1 ? 1u : (uint32_t)need;
-      if (blockIdx.x >= nb) return;
     }
     Acc a = {0, 0, 0, 0};
-    if (want_dir == kDirTD) top_down(g, w, kp, L, nb, a);
-    else bottom_up(g, w, kp, L, a);
-    if (finish_block<BT>(c, a, nb)) {
+    if (vb < nb) {
+      if (want_dir == kDirTD) top_down(g, w, kp, L, vb, nb, a);
+      else bottom_up(g, w, kp, L, a);
+    }
+    if (!finish_block_all<BT>(c, a, alone ? 1u : 0u)) return;
+    if (threadIdx.x == 0) {
       if (want_dir == kDirTD && ld_agent(&c->huge_pack) != 0ull) {
         c->aux = kAuxHuge;
       } else {
         decide(g, w, kp);
       }
     }
-    if (want_dir != kDirTD || nb != 1) return;
-    /* make thread 0's control writes and every thread's labels, bits and
+    if (want_dir != kDirTD) return;
+    /* make thread 0's control writes and every workgroup's labels, bits and
        queue entries of this level visible to the whole workgroup */
     __threadfence();
     __syncthreads();
     __threadfence();
-    /* only while the next level also fits this one workgroup */
-    if (!ld_agent(&c->q_direct) || ld_agent(&c->n_f) > (int64_t)kBlock) return;
+    if (ld_agent(&c->done) || ld_agent(&c->aux) != kAuxNone || ld_agent(&c->dir) != kDirTD ||
+        !ld_agent(&c->q_direct) || ld_agent(&c->n_f) > (int64_t)kBlock)
+      return;
   }
 }
 
@@ -762,6 +780,7 @@ __global__ void __launch_bounds__(kBlock) k_init_roots(GView g, WView w, const i
   }
   dsum = wave_sum(dsum);
   if (lane_id() == 0) s_deg[threadIdx.x / kWave] = dsum;
+  reset_groups(w.ctl);
   __syncthreads();
   if (threadIdx.x != 0) return;
   int64_t dr = 0;

@@ -50,14 +50,19 @@ __device__ __forceinline__ T ld_agent(const T* p) {
 }
 
 /* End of a workgroup's share of a level kernel: its accumulators are summed
-   and handed on, and the call returns true in thread 0 of the last
-   workgroup of the grid (or of its first `nblocks` workgroups, when only
-   those take part).  Workgroups report to one of kGroups group slots
-   (one cache line each) and the last of each group forwards the group's sums
-   to the level counters, so no address sees more than gridDim/kGroups
-   atomics. */
+   and handed on, and the call returns true in every thread of the last
+   workgroup to report.  `nblocks` workgroups report (0: the whole grid);
+   with nblocks = 1 the caller is alone and nothing is counted.  Workgroups
+   report to one of kGroups group slots (one cache line each) and the last
+   of each group forwards the group's sums to the level counters, so no
+   address sees more than gridDim/kGroups atomics.
+
+   Every workgroup that reads a level's control state must report before
+   the level can close: a workgroup that read the state and left without
+   reporting could otherwise be overtaken by the close, and one dispatched
+   after the close would read the next level's state inside this launch. */
 template <int BT = kBlock>
-__device__ bool finish_block(Ctl* c, Acc a, uint32_t nblocks = 0) {
+__device__ bool finish_block_all(Ctl* c, Acc a, uint32_t nblocks = 0) {
   __shared__ int64_t part[4][BT / kWave];
   __shared__ unsigned long long bpart[BT / kWave];
   __shared__ int is_last;
@@ -122,7 +127,26 @@ __device__ bool finish_block(Ctl* c, Acc a, uint32_t nblocks = 0) {
     }
   }
   __syncthreads();
-  return threadIdx.x == 0 && is_last;
+  return is_last != 0;
+}
+
+/* As finish_block_all, true in thread 0 of the last workgroup only. */
+template <int BT = kBlock>
+__device__ bool finish_block(Ctl* c, Acc a, uint32_t nblocks = 0) {
+  const bool last = finish_block_all<BT>(c, a, nblocks);
+  return threadIdx.x == 0 && last;
+}
+
+/* Completion groups and the grid ticket back to zero (one workgroup, before
+   any level kernel of a traversal). */
+__device__ __forceinline__ void reset_groups(Ctl* c) {
+  for (int i = threadIdx.x; i < kGroups; i += blockDim.x) {
+    GroupSlot& gs = c->grp[i];
+    for (int k = 0; k < 4; ++k) gs.sum[k] = 0;
+    gs.bits = 0ull;
+    gs.ticket = 0u;
+  }
+  if (threadIdx.x == 0) c->ticket = 0u;
 }
 
 /* Inclusive prefix sum over the wavefront. */

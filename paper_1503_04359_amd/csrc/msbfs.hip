@@ -547,6 +547,7 @@ __global__ void k_ms_init_roots(GView g, MsView m, MsRoots roots, int32_t first_
     deg = g.off[v + 1] - g.off[v];
   }
   if (b < 64) slot_start_counts(c, b, deg, g.m);
+  reset_groups(c);
   const int64_t deg_sum = wave_sum(deg);
   if (b != 0) return;
   ctl_reset(c);
@@ -617,6 +618,7 @@ __global__ void k_ms_session_seed(GView g, MsView m, MsRoots roots, SlotOuts out
 }
 
 __global__ void k_ms_session_ctl(MsView m) {
+  reset_groups(m.ctl);
   if (threadIdx.x != 0) return;
   Ctl* c = m.ctl;
   ctl_reset(c);
