@@ -462,9 +462,6 @@ def main() -> int:
     ap.add_argument("--serve-duration", type=float, default=10.0)
     ap.add_argument("--serve-drain", type=float, default=5.0)
     ap.add_argument("--serve-chunk", type=int, default=4)
-    ap.add_argument("--serve-unverified", action="store_true",
-                    help="serve mode: run it although its last run on the current kernels faulted the GPU "
-                         "(cause not found yet)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--param", action="append", default=[], metavar="NAME=VALUE",
                     help="override a dobfs_params field (e.g. alpha=14), repeatable")
@@ -496,11 +493,6 @@ def main() -> int:
                                                args.traffic)))
         return 0
 
-    if args.mode == "serve" and not args.serve_unverified:
-        print("bench.py: --mode serve is switched off: its last run on the current kernels (8 graphs served "
-              "at once on 8 streams) faulted the GPU and the cause is not found yet; pass --serve-unverified "
-              "to run it anyway.", file=sys.stderr)
-        return 3
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(the traversal is not sharded across GPUs; the result is one GPU's throughput).", file=sys.stderr)

@@ -171,7 +171,7 @@ struct dobfs_session_s {
 
 namespace {
 
-int alloc_workspace(dobfs_graph_s* g, Workspace* w) {
+int alloc_workspace(dobfs_graph_s* g, Workspace* w, hipStream_t s) {
   const int64_t W = g->words;
   hipError_t e;
   if ((e = dalloc(&w->vis, W)) != hipSuccess || (e = dalloc(&w->fr0, W)) != hipSuccess ||
@@ -185,10 +185,6 @@ int alloc_workspace(dobfs_graph_s* g, Workspace* w) {
     return fail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "workspace allocation", e);
   }
   w->log_cap = kLogCap;
-  if ((e = hipMemset(w->ctl, 0, sizeof(Ctl))) != hipSuccess) {  /* completion groups start at zero */
-    w->release();
-    return fail(DOBFS_EDEVICE, "workspace init", e);
-  }
   if ((e = hipHostMalloc(reinterpret_cast<void**>(&w->done_host), 2 * sizeof(int32_t))) != hipSuccess ||
       (e = hipEventCreateWithFlags(&w->ev[0], hipEventDisableTiming)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&w->ev[1], hipEventDisableTiming)) != hipSuccess ||
@@ -196,11 +192,24 @@ int alloc_workspace(dobfs_graph_s* g, Workspace* w) {
     w->release();
     return fail(DOBFS_EDEVICE, "workspace events", e);
   }
+  /* Completion groups start at zero.  The fill goes on the stream of the
+     run that asked for the workspace, followed by the idle event: the null
+     stream is not ordered with the caller's (non-blocking) streams, so a
+     fill there could land after that run's first kernels had set up the
+     control block; and a run that fails before launching anything still
+     leaves the workspace marked busy until the fill is done. */
+  if ((e = hipMemsetAsync(w->ctl, 0, sizeof(Ctl), s)) != hipSuccess ||
+      (e = hipEventRecord(w->idle, s)) != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    w->release();
+    return fail(DOBFS_EDEVICE, "workspace init", e);
+  }
   return DOBFS_OK;
 }
 
-/* A workspace whose previous run has drained, or a new one. */
-int acquire_workspace(dobfs_graph_s* g, Workspace** out) {
+/* A workspace whose previous run has drained, or a new one (initialised on
+   stream s, the stream its first run will use). */
+int acquire_workspace(dobfs_graph_s* g, Workspace** out, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g->mu);
   for (Workspace* w : g->pool) {
     if (w->busy) continue;
@@ -211,7 +220,7 @@ int acquire_workspace(dobfs_graph_s* g, Workspace** out) {
   }
   Workspace* w = new (std::nothrow) Workspace();
   if (!w) return fail(DOBFS_ENOMEM, "workspace");
-  const int st = alloc_workspace(g, w);
+  const int st = alloc_workspace(g, w, s);
   if (st != DOBFS_OK) {
     delete w;
     return st;
@@ -337,15 +346,17 @@ int ensure_ms_buffers(dobfs_graph_s* g, Workspace* w, int32_t k) {
   return DOBFS_OK;
 }
 
-int fill_stats(Workspace* w, hipStream_t s, dobfs_stats* stats, int64_t launches, const std::vector<float>& kms) {
+/* Stats of a finished traversal from its control block and level log. */
+int fill_stats(const Ctl* ctl_dev, const dobfs_level_rec* log_dev, int32_t log_cap, hipStream_t s,
+               dobfs_stats* stats, int64_t launches, const std::vector<float>& kms) {
   Ctl ctl;
-  DOBFS_HIP(hipMemcpyAsync(&ctl, w->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "stats copy");
+  DOBFS_HIP(hipMemcpyAsync(&ctl, ctl_dev, sizeof(Ctl), hipMemcpyDeviceToHost, s), "stats copy");
   DOBFS_HIP(hipStreamSynchronize(s), "stats sync");
   stats->level_launches = (int32_t)launches;
   stats->level_kernel_ms = 0.0;
   for (float x : kms) stats->level_kernel_ms += x;
   stats->levels = ctl.levels;
-  stats->log_len = ctl.log_len < w->log_cap ? ctl.log_len : w->log_cap;
+  stats->log_len = ctl.log_len < log_cap ? ctl.log_len : log_cap;
   stats->reached = ctl.reached;
   stats->m_c = ctl.reached_deg / 2;
   stats->checked = ctl.checked_total;
@@ -353,8 +364,9 @@ int fill_stats(Workspace* w, hipStream_t s, dobfs_stats* stats, int64_t launches
   if (stats->log && stats->log_cap > 0) {
     const int32_t k = stats->log_len < stats->log_cap ? stats->log_len : stats->log_cap;
     if (k > 0)
-      DOBFS_HIP(hipMemcpy(stats->log, w->log, sizeof(dobfs_level_rec) * (size_t)k, hipMemcpyDeviceToHost),
+      DOBFS_HIP(hipMemcpyAsync(stats->log, log_dev, sizeof(dobfs_level_rec) * (size_t)k, hipMemcpyDeviceToHost, s),
                 "log copy");
+    DOBFS_HIP(hipStreamSynchronize(s), "log copy");
     for (int32_t i = 0; i < k; ++i) stats->log[i].kernel_ms = i < (int32_t)kms.size() ? kms[(size_t)i] : 0.f;
   }
   return DOBFS_OK;
@@ -603,7 +615,7 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
       g->first_caller_tried.store(true, std::memory_order_release);
     }
   }
-  if ((st = acquire_workspace(g, &w)) != DOBFS_OK) return st;
+  if ((st = acquire_workspace(g, &w, s)) != DOBFS_OK) return st;
   RunGuard guard{g, w, s};
   if (!parent && !g->new2old) {
     if (!w->parent_scratch) {
@@ -682,7 +694,7 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
     for (int64_t i = 0; i < launches; ++i)
       DOBFS_HIP(hipEventElapsedTime(&kms[(size_t)i], w->tev[2 * i], w->tev[2 * i + 1]), "timing");
   }
-  return fill_stats(w, s, stats, launches, kms);
+  return fill_stats(w->ctl, w->log, w->log_cap, s, stats, launches, kms);
 }
 
 int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, const dobfs_params* p,
@@ -713,7 +725,7 @@ int dobfs_batch_submit(dobfs_graph_t g, const int64_t* roots, int32_t k, int32_t
   if (st != DOBFS_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Workspace* w = nullptr;
-  if ((st = acquire_workspace(g, &w)) != DOBFS_OK) return st;
+  if ((st = acquire_workspace(g, &w, s)) != DOBFS_OK) return st;
   RunGuard guard{g, w, s};
   if ((st = ensure_ms_buffers(g, w, k)) != DOBFS_OK) return st;
   const GView gv = g->view();
@@ -748,7 +760,7 @@ int dobfs_batch_submit(dobfs_graph_t g, const int64_t* roots, int32_t k, int32_t
   DOBFS_HIP(hipEventRecord(w->idle, s), "idle event");
   guard.launched = false;
   if (!stats) return DOBFS_OK;
-  return fill_stats(w, s, stats, launches, std::vector<float>());
+  return fill_stats(w->ctl, w->log, w->log_cap, s, stats, launches, std::vector<float>());
 }
 
 int dobfs_pack_upload(int32_t count, const int64_t* const* offsets, const int32_t* const* indices, const int64_t* n,
@@ -870,7 +882,7 @@ int dobfs_session_open(dobfs_graph_t g, const dobfs_params* p, void* stream, dob
     delete ss;
     return status;
   };
-  if ((st = acquire_workspace(g, &ss->w)) != DOBFS_OK) {
+  if ((st = acquire_workspace(g, &ss->w, ss->stream)) != DOBFS_OK) {
     ss->w = nullptr;
     return undo(st);
   }
@@ -963,8 +975,9 @@ int dobfs_session_step(dobfs_session_t ss, int64_t* done_tags, int32_t cap, int3
     const int32_t nlog = std::min(ss->host_ctl->log_len, m.log_cap);
     if (nlog > 0) {
       ss->last_log.resize((size_t)nlog);
-      DOBFS_HIP(hipMemcpy(ss->last_log.data(), ss->w->log, sizeof(dobfs_level_rec) * (size_t)nlog,
-                          hipMemcpyDeviceToHost), "log copy");
+      DOBFS_HIP(hipMemcpyAsync(ss->last_log.data(), ss->w->log, sizeof(dobfs_level_rec) * (size_t)nlog,
+                               hipMemcpyDeviceToHost, s), "log copy");
+      DOBFS_HIP(hipStreamSynchronize(s), "log copy");
     }
     const uint64_t ended = ss->active & ~ss->host_ctl->live;
     if (ended && g->new2old) {
