@@ -34,13 +34,6 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_serve_mode_is_switched_off_by_default():
-    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--mode", "serve"], capture_output=True,
-                       text=True, timeout=300)
-    assert r.returncode == 3
-    assert "switched off" in r.stderr
-
-
 def test_traffic_from_counters(tmp_path):
     probe = "void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add<int>>(int)"
     td = "dobfs::(anonymous namespace)::k_level_td(dobfs::GView, dobfs::WView, dobfs::KParams)"
