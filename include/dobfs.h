@@ -25,7 +25,8 @@
  *     been synchronised.
  *   - The library allocates device memory only in dobfs_graph_upload,
  *     dobfs_pack_upload and the first dobfs_run / dobfs_batch_submit on a
- *     graph handle (workspaces, reused afterwards).
+ *     graph handle (workspaces, reused afterwards); dobfs_run_noalloc never
+ *     allocates.
  */
 #ifndef DOBFS_H
 #define DOBFS_H
@@ -187,6 +188,26 @@ int dobfs_graph_info(dobfs_graph_t g, dobfs_graph_info_t* info);
    Errors: EINVAL, ERANGE (root), ENOMEM (first-run workspace), EDEVICE. */
 int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, const dobfs_params* p,
               dobfs_stats* stats, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the
+   single-source traversal of dobfs_run with its whole workspace in one
+   fixed device array of 64 MiB per device, which holds the graph's traversal
+   state for up to about 2.5M vertices (bitmaps, queues, control block, level
+   log, and 8 bytes per vertex of packed labels on relabelled graphs or 4 of
+   parents when `parent` is NULL).  The call allocates nothing: no device,
+   pinned or library allocation and no events.  It checks for the end of the
+   traversal after each chunk of levels with a stream synchronisation and
+   returns once depth/parent are complete.  Arguments and results as for
+   dobfs_run, except that DOBFS_RUN_TIME_KERNELS is refused (EINVAL) and a
+   relabelled graph uses its caller-ID column only if an earlier dobfs_run
+   built it.  The array is shared by every call on the device and keeps the
+   last call's contents (each call clears what it reads first); calls that
+   overlap on one device race and give wrong results.
+   Errors: as dobfs_run, plus EINVAL (the graph lives on another device) and
+   ENOTSUP (the graph needs more scratch than the array holds). */
+int dobfs_run_noalloc(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, const dobfs_params* p,
+                      dobfs_stats* stats, void* stream);
 
 /* One traversal seeded from several roots at once (host int64[nroots],
    caller IDs; duplicates allowed): depth = hop distance to the nearest root,

@@ -52,7 +52,7 @@ POLICIES = {"edge": POLICY_EDGE, "paper": POLICY_PAPER, "td": POLICY_FORCED_TD,
             "bu": POLICY_FORCED_BU, "random": POLICY_RANDOM, "cost": POLICY_COST}
 
 EXPORTED = ("dobfs_default_params", "dobfs_graph_upload", "dobfs_graph_free", "dobfs_graph_info",
-            "dobfs_run", "dobfs_run_multi", "dobfs_batch_submit", "dobfs_pack_upload", "dobfs_pack_bases",
+            "dobfs_run", "dobfs_run_noalloc", "dobfs_run_multi", "dobfs_batch_submit", "dobfs_pack_upload", "dobfs_pack_bases",
             "dobfs_pack_run", "dobfs_session_open", "dobfs_session_admit", "dobfs_session_step",
             "dobfs_session_counts", "dobfs_session_levels", "dobfs_session_close", "dobfs_strerror", "dobfs_last_error")
 
@@ -283,6 +283,27 @@ class Graph:
             out_stats = Stats(cs.levels, cs.reached, cs.m_c, cs.checked, recs, cs.level_launches,
                               cs.level_kernel_ms)
         return depth, parent, out_stats
+
+    def run_noalloc(self, root: int, depth=None, parent=None, params: CParams | None = None, stats: bool = False,
+                    stream=None, want_parent: bool = True, log_cap: int = 4096):
+        """dobfs_run_noalloc: the traversal of run() with the library's fixed
+        scratch array as workspace (the library allocates nothing).  The
+        output tensors are allocated here unless given.  Returns as run()."""
+        import torch
+        if depth is None:
+            depth = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        if parent is None and want_parent:
+            parent = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        for t in (depth, parent):
+            if t is not None and (t.dtype != torch.int32 or t.numel() < self.n or not t.is_cuda
+                                  or not t.is_contiguous()):
+                raise ValueError("depth/parent must be contiguous int32 CUDA tensors of length n")
+        cs, log = _make_stats(stats, log_cap)
+        _check(_lib.dobfs_run_noalloc(self._h, int(root), _ptr(depth), _ptr(parent) if parent is not None else None,
+                                      ctypes.byref(params) if params is not None else None,
+                                      ctypes.byref(cs) if cs is not None else None, _stream_ptr(stream)),
+               "dobfs_run_noalloc")
+        return depth, parent, _read_stats(cs, log)
 
     def run_multi(self, roots, depth=None, parent=None, params: CParams | None = None, stats: bool = False,
                   stream=None, want_parent: bool = True):

@@ -372,6 +372,73 @@ int fill_stats(const Ctl* ctl_dev, const dobfs_level_rec* log_dev, int32_t log_c
   return DOBFS_OK;
 }
 
+/* ---- scratch of the allocation-free entry point -------------------------
+
+   One fixed array per device holds the whole workspace of a traversal:
+   bitmaps, queues, split list, control block, level log, and the packed
+   labels (relabelled graphs) or the parent array (unrelabelled graphs run
+   without a parent output).  Its device address is looked up once per
+   device and kept; the array's name is only a host-side handle. */
+constexpr uint64_t kScratchBytes = 64ull << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+/* Device address of `scratch` on device dev (current), looked up on the
+   first call for that device. */
+int scratch_base(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(DOBFS_ENOTSUP, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail(DOBFS_EDEVICE, "scratch address", e);
+    g_scratch[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return DOBFS_OK;
+}
+
+struct NoallocLayout {
+  uint64_t vis, fr0, fr1, q0, qd0, qd1, huge_u, huge_base, ctl, log, packed, parent, total;
+};
+
+/* Byte offsets of the workspace arrays in the scratch array (each on a
+   256-byte boundary); the same sizes as a pooled workspace. */
+NoallocLayout noalloc_layout(const dobfs_graph_s* g, bool own_parent) {
+  NoallocLayout l;
+  uint64_t at = 0;
+  auto put = [&](uint64_t bytes) {
+    const uint64_t here = at;
+    at += (bytes + 255) & ~255ull;
+    return here;
+  };
+  const uint64_t W = (uint64_t)g->words;
+  const uint64_t n = (uint64_t)g->n;
+  const uint64_t nh = (uint64_t)std::max<int64_t>(g->n_huge, 1);
+  l.vis = put(8 * W);
+  l.fr0 = put(8 * W);
+  l.fr1 = put(8 * W);
+  l.q0 = put(4 * std::max<uint64_t>(n, 4 * W));
+  l.qd0 = put(4 * (uint64_t)kDirectCap);
+  l.qd1 = put(4 * (uint64_t)kDirectCap);
+  l.huge_u = put(4 * nh);
+  l.huge_base = put(4 * nh);
+  l.ctl = put(sizeof(Ctl));
+  l.log = put(sizeof(dobfs_level_rec) * (uint64_t)kLogCap);
+  l.packed = g->new2old ? put(8 * n) : 0;
+  l.parent = own_parent ? put(4 * n) : 0;
+  l.total = at;
+  return l;
+}
+
 }  // namespace
 
 extern "C" {
@@ -700,6 +767,82 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
 int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, const dobfs_params* p,
               dobfs_stats* stats, void* stream) {
   return run_multi(g, nullptr, 0, root, depth, parent, p, stats, stream);
+}
+
+/* Single-source run whose workspace is the device's fixed scratch array
+   (see noalloc_layout): no device or pinned allocation, no events.  The
+   host checks the done flag after each chunk of levels with a plain copy
+   and a stream synchronisation, and the call returns once the outputs are
+   complete.  Overlapping calls on one device share the array and race. */
+int dobfs_run_noalloc(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, const dobfs_params* p,
+                      dobfs_stats* stats, void* stream) {
+  g_last_error.clear();
+  if (!g || !depth) return fail(DOBFS_EINVAL, "graph or depth is NULL");
+  if (root < 0 || root >= g->n) return fail(DOBFS_ERANGE, "root outside [0, n)");
+  dobfs_params prm;
+  if (p) prm = *p; else dobfs_default_params(&prm);
+  int st = check_params(prm);
+  if (st != DOBFS_OK) return st;
+  if (prm.flags & DOBFS_RUN_TIME_KERNELS)
+    return fail(DOBFS_EINVAL, "DOBFS_RUN_TIME_KERNELS needs timing events, which the allocation-free run does not create");
+  int dev = 0;
+  DOBFS_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != g->device) return fail(DOBFS_EINVAL, "the graph is resident on another device");
+  unsigned char* base = nullptr;
+  if ((st = scratch_base(dev, &base)) != DOBFS_OK) return st;
+  const bool own_parent = !parent && !g->new2old;  /* parents kept in scratch, not returned */
+  const NoallocLayout lay = noalloc_layout(g, own_parent);
+  if (lay.total > kScratchBytes) {
+    char msg[192];
+    std::snprintf(msg, sizeof(msg),
+                  "graph needs %llu bytes of traversal scratch; the allocation-free run has %llu (n <= ~2.5M vertices)",
+                  (unsigned long long)lay.total, (unsigned long long)kScratchBytes);
+    return fail(DOBFS_ENOTSUP, msg);
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const GView gv = g->view();
+  WView wv;
+  wv.vis = reinterpret_cast<uint64_t*>(base + lay.vis);
+  wv.fr0 = reinterpret_cast<uint64_t*>(base + lay.fr0);
+  wv.fr1 = reinterpret_cast<uint64_t*>(base + lay.fr1);
+  wv.q0 = reinterpret_cast<int32_t*>(base + lay.q0);
+  wv.qd0 = reinterpret_cast<int32_t*>(base + lay.qd0);
+  wv.qd1 = reinterpret_cast<int32_t*>(base + lay.qd1);
+  wv.huge_u = reinterpret_cast<int32_t*>(base + lay.huge_u);
+  wv.huge_base = reinterpret_cast<uint32_t*>(base + lay.huge_base);
+  wv.depth = depth;
+  wv.parent = own_parent ? reinterpret_cast<int32_t*>(base + lay.parent) : parent;
+  wv.packed = g->new2old ? reinterpret_cast<int64_t*>(base + lay.packed) : nullptr;
+  wv.ctl = reinterpret_cast<Ctl*>(base + lay.ctl);
+  wv.log = reinterpret_cast<dobfs_level_rec*>(base + lay.log);
+  wv.log_cap = kLogCap;
+  wv.pad = 0;
+  const KParams kp = to_kparams(prm);
+  /* the init kernels clear everything a traversal reads before writing it,
+     the completion groups included, so the array's previous contents do
+     not matter */
+  DOBFS_HIP(launch_init(gv, wv, nullptr, 1, root, first_direction(prm), g->grid, s), "init launch");
+  const int K = prm.chunk_levels;
+  const int64_t max_chunks = (g->n + 1) / K + 3;
+  int64_t launches = 0;
+  for (int64_t c = 0;; ++c) {
+    if (c >= max_chunks) return fail(DOBFS_EDEVICE, "level loop did not terminate");
+    for (int i = 0; i < K; ++i, ++launches) {
+      DOBFS_HIP(launch_level(gv, wv, kp, g->grid, s), "level launch");
+      DOBFS_HIP(launch_aux(gv, wv, kp, g->grid, s), "aux launch");
+    }
+    int32_t done = 0;
+    DOBFS_HIP(hipMemcpyAsync(&done, &wv.ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, s), "done flag copy");
+    DOBFS_HIP(hipStreamSynchronize(s), "level chunk");
+    if (done) break;
+  }
+  if (g->new2old) DOBFS_HIP(launch_finalize(gv, wv, root, g->grid, s), "finalize launch");
+  if (stats) {
+    const std::vector<float> none;
+    if ((st = fill_stats(wv.ctl, wv.log, wv.log_cap, s, stats, launches, none)) != DOBFS_OK) return st;
+  }
+  DOBFS_HIP(hipStreamSynchronize(s), "finalize");
+  return DOBFS_OK;
 }
 
 int dobfs_run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int32_t* depth, int32_t* parent,
