@@ -65,8 +65,9 @@ typedef struct dobfs_graph_s* dobfs_graph_t; /* opaque, library-owned */
 
 /* ---- run flags (dobfs_params.flags) --------------------------------------- */
 #define DOBFS_RUN_TIME_KERNELS 0x1u /* bracket every level-kernel launch with
-                                      HIP events on `stream`; the durations
-                                      are reported in dobfs_stats            */
+                                      HIP events on `stream`; the summed
+                                      durations per kernel are reported in
+                                      dobfs_stats                           */
 
 /* ---- direction policies (Section 3.3) ------------------------------------ */
 #define DOBFS_POLICY_EDGE 0      /* top-down -> bottom-up when the next
@@ -122,7 +123,7 @@ typedef struct {
   int64_t found;           /* vertices of depth L+1                          */
   int64_t found_deg;       /* their summed degree                            */
   uint64_t t_end;          /* device wall clock (100 MHz) at level end       */
-  float kernel_ms;         /* level-kernel duration (DOBFS_RUN_TIME_KERNELS) */
+  float kernel_ms;         /* reserved, 0                                    */
   int32_t reserved;
 } dobfs_level_rec;
 
@@ -136,10 +137,16 @@ typedef struct {
   uint64_t t_begin;        /* device wall clock at init                      */
   dobfs_level_rec* log;    /* caller's host array, or NULL                   */
   int32_t log_cap;         /* its capacity in records                        */
-  int32_t level_launches;  /* level-kernel launches, including those that
-                              found the traversal finished and returned     */
-  double level_kernel_ms;  /* summed duration of those launches
+  int32_t level_launches;  /* level slots enqueued: each launches the
+                              top-down kernel, the bottom-up kernel and the
+                              aux kernel (split rows, frontier conversion);
+                              the ones not needed, or launched after the
+                              traversal finished, return at once           */
+  double level_kernel_ms;  /* summed duration of all those launches
                               (DOBFS_RUN_TIME_KERNELS, else 0)              */
+  double td_kernel_ms;     /* ... of the top-down kernel's launches         */
+  double bu_kernel_ms;     /* ... of the bottom-up kernel's launches        */
+  double aux_kernel_ms;    /* ... of the aux kernel's launches              */
 } dobfs_stats;
 
 typedef struct {

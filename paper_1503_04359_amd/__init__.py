@@ -85,7 +85,9 @@ class CStats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("log_len", ctypes.c_int32), ("reached", ctypes.c_int64),
                 ("m_c", ctypes.c_int64), ("checked", ctypes.c_int64), ("t_begin", ctypes.c_uint64),
                 ("log", ctypes.POINTER(LevelRec)), ("log_cap", ctypes.c_int32),
-                ("level_launches", ctypes.c_int32), ("level_kernel_ms", ctypes.c_double)]
+                ("level_launches", ctypes.c_int32), ("level_kernel_ms", ctypes.c_double),
+                ("td_kernel_ms", ctypes.c_double), ("bu_kernel_ms", ctypes.c_double),
+                ("aux_kernel_ms", ctypes.c_double)]
 
 
 class CGraphInfo(ctypes.Structure):
@@ -166,6 +168,10 @@ class Stats:
     log: list = field(default_factory=list)
     level_launches: int = 0
     level_kernel_ms: float = 0.0
+    td_kernel_ms: float = 0.0
+    bu_kernel_ms: float = 0.0
+    aux_kernel_ms: float = 0.0
+    log_len: int = 0
 
     def dirs(self) -> list[int]:
         return [r["dir"] for r in self.log]
@@ -185,7 +191,8 @@ def _read_stats(cs, log):
     if cs is None:
         return None
     recs = [{f: getattr(log[i], f) for f, _ in LevelRec._fields_} for i in range(cs.log_len)]
-    return Stats(cs.levels, cs.reached, cs.m_c, cs.checked, recs, cs.level_launches, cs.level_kernel_ms)
+    return Stats(cs.levels, cs.reached, cs.m_c, cs.checked, recs, cs.level_launches, cs.level_kernel_ms,
+                 cs.td_kernel_ms, cs.bu_kernel_ms, cs.aux_kernel_ms, cs.log_len)
 
 
 def _stream_ptr(stream):
@@ -266,22 +273,12 @@ class Graph:
             if t is not None and (t.dtype != torch.int32 or t.numel() < self.n or not t.is_cuda
                                   or not t.is_contiguous()):
                 raise ValueError("depth/parent must be contiguous int32 CUDA tensors of length n")
-        cs = None
-        log = None
-        if stats:
-            log = (LevelRec * log_cap)()
-            cs = CStats()
-            cs.log = ctypes.cast(log, ctypes.POINTER(LevelRec))
-            cs.log_cap = log_cap
+        cs, log = _make_stats(stats, log_cap)
         st = _lib.dobfs_run(self._h, int(root), _ptr(depth), _ptr(parent) if parent is not None else None,
                             ctypes.byref(params) if params is not None else None,
                             ctypes.byref(cs) if cs is not None else None, _stream_ptr(stream))
         _check(st, "dobfs_run")
-        out_stats = None
-        if stats:
-            recs = [{k: getattr(log[i], k) for k, _ in LevelRec._fields_} for i in range(cs.log_len)]
-            out_stats = Stats(cs.levels, cs.reached, cs.m_c, cs.checked, recs, cs.level_launches,
-                              cs.level_kernel_ms)
+        out_stats = _read_stats(cs, log)
         return depth, parent, out_stats
 
     def run_noalloc(self, root: int, depth=None, parent=None, params: CParams | None = None, stats: bool = False,
@@ -334,20 +331,12 @@ class Graph:
             depth = torch.empty((k, self.n), dtype=torch.int32, device="cuda")
         if depth.dtype != torch.int32 or depth.numel() < k * self.n or not depth.is_cuda or not depth.is_contiguous():
             raise ValueError("depth must be a contiguous int32 CUDA tensor of k*n elements")
-        cs = log = None
-        if stats:
-            log = (LevelRec * log_cap)()
-            cs = CStats()
-            cs.log = ctypes.cast(log, ctypes.POINTER(LevelRec))
-            cs.log_cap = log_cap
+        cs, log = _make_stats(stats, log_cap)
         _check(_lib.dobfs_batch_submit(self._h, r.ctypes.data, k, _ptr(depth),
                                        ctypes.byref(params) if params is not None else None,
                                        ctypes.byref(cs) if cs is not None else None, _stream_ptr(stream)),
                "dobfs_batch_submit")
-        out = None
-        if stats:
-            recs = [{f: getattr(log[i], f) for f, _ in LevelRec._fields_} for i in range(cs.log_len)]
-            out = Stats(cs.levels, cs.reached, cs.m_c, cs.checked, recs, cs.level_launches, cs.level_kernel_ms)
+        out = _read_stats(cs, log)
         return depth, out
 
     def session(self, params: CParams | None = None, stream=None) -> "Session":

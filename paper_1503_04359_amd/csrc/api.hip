@@ -353,8 +353,13 @@ int fill_stats(const Ctl* ctl_dev, const dobfs_level_rec* log_dev, int32_t log_c
   DOBFS_HIP(hipMemcpyAsync(&ctl, ctl_dev, sizeof(Ctl), hipMemcpyDeviceToHost, s), "stats copy");
   DOBFS_HIP(hipStreamSynchronize(s), "stats sync");
   stats->level_launches = (int32_t)launches;
-  stats->level_kernel_ms = 0.0;
-  for (float x : kms) stats->level_kernel_ms += x;
+  stats->level_kernel_ms = stats->td_kernel_ms = stats->bu_kernel_ms = stats->aux_kernel_ms = 0.0;
+  for (size_t i = 0; i + 2 < kms.size(); i += 3) {
+    stats->td_kernel_ms += kms[i];
+    stats->bu_kernel_ms += kms[i + 1];
+    stats->aux_kernel_ms += kms[i + 2];
+  }
+  stats->level_kernel_ms = stats->td_kernel_ms + stats->bu_kernel_ms + stats->aux_kernel_ms;
   stats->levels = ctl.levels;
   stats->log_len = ctl.log_len < log_cap ? ctl.log_len : log_cap;
   stats->reached = ctl.reached;
@@ -367,7 +372,7 @@ int fill_stats(const Ctl* ctl_dev, const dobfs_level_rec* log_dev, int32_t log_c
       DOBFS_HIP(hipMemcpyAsync(stats->log, log_dev, sizeof(dobfs_level_rec) * (size_t)k, hipMemcpyDeviceToHost, s),
                 "log copy");
     DOBFS_HIP(hipStreamSynchronize(s), "log copy");
-    for (int32_t i = 0; i < k; ++i) stats->log[i].kernel_ms = i < (int32_t)kms.size() ? kms[(size_t)i] : 0.f;
+    for (int32_t i = 0; i < k; ++i) stats->log[i].kernel_ms = 0.f;
   }
   return DOBFS_OK;
 }
@@ -730,18 +735,27 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
   DOBFS_HIP(launch_init(gv, wv, roots_dev, roots ? nroots : 1, root, first_direction(prm), g->grid, s),
             "init launch");
   const bool timed = (prm.flags & DOBFS_RUN_TIME_KERNELS) != 0;
+  /* timed runs bracket each of the slot's three kernels with events:
+     tev[4i] k_level_td tev[4i+1] k_level_bu tev[4i+2] k_aux tev[4i+3] */
   auto level = [&](int64_t i) -> int {
-    if (timed) {
-      while ((int64_t)w->tev.size() < 2 * (i + 1)) {
-        hipEvent_t ev;
-        DOBFS_HIP(hipEventCreate(&ev), "timing event");
-        w->tev.push_back(ev);
-      }
-      DOBFS_HIP(hipEventRecord(w->tev[2 * i], s), "timing event");
+    if (!timed) {
+      DOBFS_HIP(launch_level(gv, wv, kp, g->grid, s), "level launch");
+      DOBFS_HIP(launch_aux(gv, wv, kp, g->grid, s), "aux launch");
+      return DOBFS_OK;
     }
-    DOBFS_HIP(launch_level(gv, wv, kp, g->grid, s), "level launch");
-    if (timed) DOBFS_HIP(hipEventRecord(w->tev[2 * i + 1], s), "timing event");
+    while ((int64_t)w->tev.size() < 4 * (i + 1)) {
+      hipEvent_t ev;
+      DOBFS_HIP(hipEventCreate(&ev), "timing event");
+      w->tev.push_back(ev);
+    }
+    hipEvent_t* ev = &w->tev[4 * i];
+    DOBFS_HIP(hipEventRecord(ev[0], s), "timing event");
+    DOBFS_HIP(launch_level_td(gv, wv, kp, g->grid, s), "level launch");
+    DOBFS_HIP(hipEventRecord(ev[1], s), "timing event");
+    DOBFS_HIP(launch_level_bu(gv, wv, kp, g->grid, s), "level launch");
+    DOBFS_HIP(hipEventRecord(ev[2], s), "timing event");
     DOBFS_HIP(launch_aux(gv, wv, kp, g->grid, s), "aux launch");
+    DOBFS_HIP(hipEventRecord(ev[3], s), "timing event");
     return DOBFS_OK;
   };
   int64_t launches = 0;
@@ -753,13 +767,15 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
   DOBFS_HIP(hipEventRecord(w->idle, s), "idle event");
   guard.launched = false;
   if (!stats) return DOBFS_OK;
-  std::vector<float> kms;
+  std::vector<float> kms;  /* per slot: k_level_td, k_level_bu, k_aux */
   if (timed) {
     /* the lookahead chunk may still be running: wait before reading its events */
     DOBFS_HIP(hipEventSynchronize(w->idle), "timing wait");
-    kms.resize((size_t)launches);
+    kms.resize((size_t)(3 * launches));
     for (int64_t i = 0; i < launches; ++i)
-      DOBFS_HIP(hipEventElapsedTime(&kms[(size_t)i], w->tev[2 * i], w->tev[2 * i + 1]), "timing");
+      for (int k = 0; k < 3; ++k)
+        DOBFS_HIP(hipEventElapsedTime(&kms[(size_t)(3 * i + k)], w->tev[4 * i + k], w->tev[4 * i + k + 1]),
+                  "timing");
   }
   return fill_stats(w->ctl, w->log, w->log_cap, s, stats, launches, kms);
 }

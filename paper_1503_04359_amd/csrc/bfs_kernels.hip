@@ -908,13 +908,23 @@ hipError_t launch_fix_roots(const WView& w, const int32_t* roots, int32_t nroots
   return hipGetLastError();
 }
 
-hipError_t launch_level(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s) {
-  /* a top-down level that ends by deciding bottom-up lets the next level
-     run in the same slot */
+hipError_t launch_level_td(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_level_td, dim3(grid), dim3(kBlock), 0, s, g, w, kp);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_bu(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_level_bu, dim3((grid + kBuBlock / kBlock - 1) / (kBuBlock / kBlock)), dim3(kBuBlock), 0, s,
                      g, w, kp);
   return hipGetLastError();
+}
+
+hipError_t launch_level(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s) {
+  /* a top-down level that ends by deciding bottom-up lets the next level
+     run in the same slot */
+  const hipError_t e = launch_level_td(g, w, kp, grid, s);
+  if (e != hipSuccess) return e;
+  return launch_level_bu(g, w, kp, grid, s);
 }
 
 hipError_t launch_finalize(const GView& g, const WView& w, int64_t root, int grid, hipStream_t s) {

@@ -215,6 +215,9 @@ hipError_t launch_init(const GView& g, const WView& w, const int32_t* roots, int
                        int32_t first_dir, int grid, hipStream_t s);
 hipError_t launch_fix_roots(const WView& w, const int32_t* roots, int32_t nroots, hipStream_t s);
 hipError_t launch_level(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s);
+/* the two halves of launch_level, for timing each kernel on its own */
+hipError_t launch_level_td(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s);
+hipError_t launch_level_bu(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s);
 hipError_t launch_aux(const GView& g, const WView& w, const KParams& kp, int grid, hipStream_t s);
 hipError_t launch_finalize(const GView& g, const WView& w, int64_t root, int grid, hipStream_t s);
 hipError_t level_grid(int* grid);
