@@ -41,31 +41,47 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GTEPS (harmonic mean over roots) at scale 30; served queries/s + p99 vs plain"
 HBM_PEAK_GBS = 8000.0
-# the level step: both direction kernels are launched for every level and the
-# one not matching the level's direction returns at once; a "launch" below is
-# that pair
-LEVEL_KERNEL = "k_level_td+k_level_bu"
+# the kernel the line's roofline is reported for: the bottom-up level kernel,
+# the largest share of a scale-30 traversal's time
+DOMINANT = "k_level_bu"
+TRAFFIC_KERNELS = ("k_level_bu", "k_level_td", "k_aux", "k_finalize")
+DIRECT_CAP = 1 << 16  # a top-down level whose frontier has at most this many edges hands its queue on directly
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def level_bytes(rec: dict, words_active: int) -> float:
-    """Algorithmic bytes of one level of the level kernel.
+def bottom_up_bytes(rec: dict, words_active: int) -> float:
+    """Algorithmic bytes of one bottom-up level: visited word read and
+    next-frontier word write (16) per active 64-vertex word; one offset (8)
+    per scanned vertex; one neighbour ID (4) and one frontier-bit probe (1/8)
+    per examined edge up to the first hit; depth and parent (8) per new
+    vertex."""
+    return 16.0 * words_active + 8.0 * rec["scanned"] + (4.0 + 0.125) * rec["checked"] + 8.0 * rec["found"]
 
-    top-down: queue entry (4) + two offsets (16) per frontier vertex; one
-      neighbour ID (4) and one visited-bit probe (1/8) per examined edge;
-      per new vertex its two offsets (16), depth, parent and queue entry (12)
-      and its visited and frontier bits (2/8).
-    bottom-up: visited word read and next-frontier word write (16) per
-      active 64-vertex word; one offset (8) per scanned vertex; one neighbour
-      ID (4) and one frontier-bit probe (1/8) per examined edge; depth and
-      parent (8) per new vertex.
-    """
-    if rec["dir"] == 0:
-        return (20.0 * rec["n_f"] + (4.0 + 0.125) * rec["checked"] + (28.0 + 0.25) * rec["found"])
-    return (16.0 * words_active + 8.0 * rec["scanned"] + (4.0 + 0.125) * rec["checked"] + 8.0 * rec["found"])
+
+def top_down_bytes(rec: dict) -> float:
+    """Algorithmic bytes of one top-down level: queue entry (4) and two
+    offsets (16) per frontier vertex; one neighbour ID (4) and one
+    visited-bit probe (1/8) per examined edge; per new vertex its two offsets
+    (16), depth, parent and queue entry (12) and its visited and frontier bits
+    (2/8)."""
+    return 20.0 * rec["n_f"] + (4.0 + 0.125) * rec["checked"] + (28.0 + 0.25) * rec["found"]
+
+
+def to_queue_bytes(log_recs: list, i: int, words_active: int) -> float:
+    """Bytes of the frontier conversion before top-down level i (bitmap read,
+    the other bitmap cleared: 16 per active word; 4 per queued vertex), which
+    runs unless level i-1 was top-down and small enough to hand its queue on
+    directly."""
+    rec = log_recs[i]
+    if rec["dir"] != 0 or i == 0:
+        return 0.0
+    prev = log_recs[i - 1]
+    if prev["dir"] == 0 and prev["m_f"] <= DIRECT_CAP:
+        return 0.0
+    return 16.0 * words_active + 4.0 * rec["n_f"]
 
 
 def kernel_source_digest() -> str:
@@ -88,28 +104,72 @@ def harmonic_mean(xs):
     return len(xs) / sum(1.0 / x for x in xs)
 
 
-def cpu_baseline(scale: int, seed: int, nroots: int) -> dict:
-    """The oracle (serial queue BFS, one thread) on a bounded sample."""
+def host_spec() -> dict:
+    """CPU model, logical CPUs and memory of the host the baseline ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem_gib = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    mem_gib = round(int(line.split()[1]) / (1 << 20), 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_allowed": len(os.sched_getaffinity(0)),
+            "mem_gib": mem_gib}
+
+
+def cpu_baseline(scale: int, seed: int, nroots: int, budget_s: float) -> dict:
+    """The oracle (serial queue BFS, one thread pinned to one core) on a
+    bounded sample of the workload: a Kronecker graph of the same family
+    and seed at a smaller scale (the scale-30 graph needs ~145 GB of host
+    memory and minutes per root), built on the device (bit-identical to the
+    host builder) and copied to the host; roots drawn as for the GPU run,
+    taken in order until `budget_s` seconds of oracle time are spent."""
     import graphgen as gg
     import oracle
     t0 = time.time()
-    g = gg.kronecker(scale, seed=seed)
-    log(f"[cpu] host-built kronecker scale {scale} in {time.time() - t0:.1f}s (n={g.n}, m={g.m})")
-    roots = gg.sample_roots(g, nroots, seed=seed + 1_000_000)
-    teps = []
-    total = 0.0
-    for r in roots:
-        t = time.perf_counter()
-        d, _ = oracle.bfs(g.offsets, g.indices, int(r))
-        dt = time.perf_counter() - t
-        total += dt
-        teps.append(oracle.traversed_edges(g.offsets, d) / dt)
+    dg = gg.kronecker_device(scale, seed=seed)
+    roots = gg.sample_roots_device(dg, nroots, seed=seed + 1_000_000)
+    g = dg.to_host()
+    dg.free()
+    log(f"[cpu] kronecker scale {scale} built on the device and copied to the host in {time.time() - t0:.1f}s "
+        f"(n={g.n}, m={g.m})")
+    spec = host_spec()
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[0]
+    os.sched_setaffinity(0, {core})
+    teps, used = [], 0.0
+    try:
+        for r in roots:
+            t = time.perf_counter()
+            d, _ = oracle.bfs(g.offsets, g.indices, int(r))
+            dt = time.perf_counter() - t
+            used += dt
+            teps.append(oracle.traversed_edges(g.offsets, d) / dt)
+            if used >= budget_s:
+                break
+    finally:
+        os.sched_setaffinity(0, set(allowed))
     val = harmonic_mean(teps) / 1e9
-    log(f"[cpu] oracle {nroots} roots in {total:.1f}s: {val:.4f} GTEPS")
+    log(f"[cpu] oracle, {len(teps)} roots on core {core} in {used:.1f}s: {val:.4f} GTEPS "
+        f"({spec['cpu_model']}, {spec['nproc']} CPUs, {spec['mem_gib']} GiB)")
     return {"value": round(val, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"serial queue BFS (one thread) over a host-built Kronecker graph of scale {scale} "
-                      f"(edgefactor 16, same initiator, seed {seed}), {nroots} roots drawn as for the GPU run, "
-                      f"harmonic mean; {total:.1f}s of CPU time"}
+            "sample": f"serial queue BFS, one thread pinned to CPU {core}, over the Kronecker graph of scale {scale} "
+                      f"(edgefactor 16, same initiator and seed {seed}; n={g.n}, m={g.m}) standing in for scale 30, "
+                      f"whose host copy would need ~145 GB and minutes per root; the first {len(teps)} of "
+                      f"{nroots} roots drawn as for the GPU run (until {budget_s:.0f}s of oracle time), "
+                      f"harmonic mean; {used:.1f}s of CPU time",
+            "scale": scale, "roots": len(teps), "seconds": round(used, 2), "host": spec}
 
 
 def _timed(stream, fn):
@@ -408,16 +468,15 @@ def bench_serve(args) -> dict:
 
 
 def traffic_from_counters(fetch_csv: str, write_csv: str, probe_bytes: int, key: str, out_path: str) -> dict:
-    """HBM bytes per level-kernel launch from two rocprofv3 --pmc runs of the
-    same command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
-    scaled by what the counter reads for the copy probe, whose kernel reads
-    and writes `probe_bytes` bytes."""
+    """HBM bytes per launch of each traversal kernel from two rocprofv3
+    --pmc runs of the same command (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch), each scaled by what the counter reads for the copy probe,
+    whose kernel reads and writes `probe_bytes` bytes."""
     import csv
 
     def load(path, counter):
-        """Copy-probe reading, summed level-kernel readings, level slots (one
-        k_level_bu dispatch per slot)."""
-        probe, level, slots = [], 0.0, 0
+        """Copy-probe reading, then per kernel: summed readings and launches."""
+        probe, per = [], {k: [0.0, 0] for k in TRAFFIC_KERNELS}
         with open(path) as f:
             for r in csv.DictReader(f):
                 if r["Counter_Name"] != counter:
@@ -425,20 +484,28 @@ def traffic_from_counters(fetch_csv: str, write_csv: str, probe_bytes: int, key:
                 name, val = r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0
                 if "CUDAFunctorOnSelf_add" in name:
                     probe.append(val)
-                elif "k_level_td(" in name or "k_level_bu(" in name:
-                    level += val
-                    slots += "k_level_bu(" in name
-        if not probe or not slots:
-            raise ValueError(f"{path}: no copy-probe or level-kernel dispatches for {counter}")
-        return probe[0], level, slots
+                    continue
+                for k in TRAFFIC_KERNELS:
+                    if f"{k}(" in name:
+                        per[k][0] += val
+                        per[k][1] += 1
+        if not probe or not per[DOMINANT][1]:
+            raise ValueError(f"{path}: no copy-probe or {DOMINANT} dispatches for {counter}")
+        return probe[0], per
 
-    pf, lf, nf = load(fetch_csv, "FETCH_SIZE")
-    pw, lw, nw = load(write_csv, "WRITE_SIZE")
+    pf, fetch = load(fetch_csv, "FETCH_SIZE")
+    pw, write = load(write_csv, "WRITE_SIZE")
     kf, kw = probe_bytes / pf, probe_bytes / pw
-    per_launch = lf * kf / nf + lw * kw / nw
-    ent = {"kernel": LEVEL_KERNEL, "source_sha256": kernel_source_digest(), "bytes_per_launch": round(per_launch),
-           "fetch_factor": round(kf, 4), "write_factor": round(kw, 4), "launches": nf,
-           "fetch_bytes_per_launch": round(lf * kf / nf), "write_bytes_per_launch": round(lw * kw / nw)}
+    kernels = {}
+    for k in TRAFFIC_KERNELS:
+        (fv, fn), (wv, wn) = fetch[k], write[k]
+        if not fn or not wn:
+            continue
+        kernels[k] = {"launches": fn, "fetch_bytes_per_launch": round(fv * kf / fn),
+                      "write_bytes_per_launch": round(wv * kw / wn),
+                      "bytes_per_launch": round(fv * kf / fn + wv * kw / wn)}
+    ent = {"source_sha256": kernel_source_digest(), "fetch_factor": round(kf, 4), "write_factor": round(kw, 4),
+           "kernels": kernels}
     data = {}
     if os.path.exists(out_path):
         with open(out_path) as f:
@@ -474,9 +541,11 @@ def main() -> int:
     ap.add_argument("--policy", default="edge")
     ap.add_argument("--reindex", choices=("on", "off"), default="on",
                     help="degree relabelling inside the library (outputs stay in caller labels)")
-    ap.add_argument("--cpu-scale", type=int, default=22)
+    ap.add_argument("--cpu-scale", type=int, default=26)
     ap.add_argument("--cpu-roots", type=int, default=16)
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tuned", action="store_true", help="library defaults instead of the autotuned parameters")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per level-kernel launch (rocprofv3 --pmc), if present")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -542,68 +611,108 @@ def main() -> int:
     depth = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
     overrides = {k: int(v) for k, v in (kv.split("=", 1) for kv in args.param)}
-    params = dobfs.make_params(args.policy, flags=dobfs.RUN_TIME_KERNELS, **overrides)
+    # parameters chosen by the autotuner on its own roots (never these), for
+    # the configuration it tuned: degree relabel on, the edge-count rule
+    from paper_1503_04359_amd import autotune
+    tuned = None
+    if not args.no_tuned and reindex and args.policy == "edge":
+        tuned = autotune.load_tuned(autotune.tuned_path(args.scale, args.edgefactor))
+    eff = dict(tuned["params"]) if tuned else {}
+    eff.update(overrides)
+    params = dobfs.make_params(args.policy, **eff)
+    # a separate step, not counted in the metric, brackets every level-kernel
+    # launch with events for the per-kernel roofline
+    params_prof = dobfs.make_params(args.policy, flags=dobfs.RUN_TIME_KERNELS, **eff)
+    if tuned:
+        log(f"[gpu] tuned parameters {tuned['params']} ({os.path.relpath(autotune.tuned_path(args.scale, args.edgefactor), ROOT)})")
 
-    def one_step(record):
+    def one_step(record, prm):
         for r in roots:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            _, _, st = dg.run(int(r), depth, parent, params=params, stats=True, stream=stream)
+            _, _, st = dg.run(int(r), depth, parent, params=prm, stats=True, stream=stream)
             e1.record(stream)
             record.append((int(r), e0, e1, st))
 
     for _ in range(args.warmup):
-        one_step([])
+        one_step([], params)
     torch.cuda.synchronize()
     runs: list = []
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        one_step(runs)
+        one_step(runs, params)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    prof: list = []
+    one_step(prof, params_prof)
+    torch.cuda.synchronize()
 
     teps, times, lines = [], [], {}
-    tot_bytes = tot_kms = 0.0
-    tot_launch = 0
     for r, e0, e1, st in runs:
         ms = e0.elapsed_time(e1)
         times.append(ms)
         teps.append(st.m_c / (ms * 1e-3))
-        tot_bytes += sum(level_bytes(rec, words_active) for rec in st.log)
-        tot_kms += st.level_kernel_ms
-        tot_launch += st.level_launches
         lines.setdefault(r, (st.levels, st.m_c, [rec["dir"] for rec in st.log]))
+    bu_bytes = td_bytes = 0.0
+    bu_ms = td_ms = aux_ms = 0.0
+    launches = 0
+    for r, _, _, st in prof:
+        if st.log_len != st.levels:
+            raise RuntimeError(f"root {r}: level log truncated ({st.log_len} of {st.levels})")
+        for i, rec in enumerate(st.log):
+            if rec["dir"] == 1:
+                bu_bytes += bottom_up_bytes(rec, words_active)
+            else:
+                td_bytes += top_down_bytes(rec) + to_queue_bytes(st.log, i, words_active)
+        bu_ms += st.bu_kernel_ms
+        td_ms += st.td_kernel_ms
+        aux_ms += st.aux_kernel_ms
+        launches += st.level_launches
     gteps = harmonic_mean(teps) / 1e9
     ms_per_step = sum(times) / args.steps
     for r, (lv, mc, dirs) in lines.items():
         rt = [t for (rr, _, _, _), t in zip(runs, times) if rr == r]
         log(f"[gpu] root {r}: levels {lv} m_c {mc} dirs {''.join('TB'[d] for d in dirs)} "
             f"best {min(rt):.3f} ms -> {mc / min(rt) / 1e6:.1f} GTEPS")
-    avg_ms = tot_kms / max(1, tot_launch)
-    per_launch = tot_bytes / max(1, tot_launch)
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = None
+    # the dominant kernel: k_level_bu is launched once per level slot; a slot
+    # whose level is top-down finds it so and returns at once, and those
+    # launches count in both the launch count and the summed duration
+    bu_avg_ms = bu_ms / max(1, launches)
+    bu_per_launch = bu_bytes / max(1, launches)
+    achieved = bu_per_launch / (bu_avg_ms * 1e-3) / 1e9 if bu_avg_ms > 0 else 0.0
+    td_gbs = td_bytes / ((td_ms + aux_ms) * 1e-3) / 1e9 if td_ms + aux_ms > 0 else 0.0
+    traffic = traffic_src = None
     if os.path.exists(args.traffic):
         try:
             with open(args.traffic) as f:
                 tr = json.load(f)
             key = f"kron-s{args.scale}-ef{args.edgefactor}-seed{args.seed}/{args.policy}/reindex-{args.reindex}"
             ent = tr.get(key, {})
-            if ent.get("kernel") == LEVEL_KERNEL and ent.get("source_sha256") == kernel_source_digest():
-                traffic = ent["bytes_per_launch"]
-        except (OSError, ValueError):
-            traffic = None
-    roofline = {"bound": "hbm", "kernel": LEVEL_KERNEL, "source_sha256": kernel_source_digest()[:16], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_launch": round(per_launch), "avg_launch_ms": round(avg_ms, 5),
-                "launches": tot_launch}
+            if ent.get("source_sha256") == kernel_source_digest():
+                traffic = ent["kernels"][DOMINANT]["bytes_per_launch"]
+                traffic_src = {k: v["bytes_per_launch"] for k, v in ent["kernels"].items()}
+        except (OSError, ValueError, KeyError):
+            traffic = traffic_src = None
+    roofline = {"bound": "hbm", "kernel": DOMINANT, "source_sha256": kernel_source_digest()[:16],
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_launch": round(bu_per_launch), "avg_launch_ms": round(bu_avg_ms, 5),
+                "launches": launches,
+                "top_down_path": {"kernels": "k_level_td+k_aux", "bytes": round(td_bytes),
+                                  "ms": round(td_ms + aux_ms, 3), "achieved": round(td_gbs, 1),
+                                  "frac": round(td_gbs / HBM_PEAK_GBS, 4)},
+                "measured_traffic_per_launch": traffic_src}
     log(f"[gpu] {gteps:.1f} GTEPS harmonic mean; wall {wall:.2f}s for {args.steps} steps; "
-        f"level kernel {achieved:.0f} GB/s algorithmic over {tot_launch} launches")
+        f"{DOMINANT} {achieved:.0f} GB/s algorithmic ({bu_ms:.1f} ms over {launches} launches); "
+        f"top-down path {td_gbs:.0f} GB/s ({td_ms + aux_ms:.1f} ms)")
+    dg.free()
+    if not reindex:
+        g.free()
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_scale, args.seed, args.cpu_roots)
+        cpu = cpu_baseline(args.cpu_scale, args.seed, args.cpu_roots, args.cpu_budget)
 
     out = {"metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
@@ -613,11 +722,12 @@ def main() -> int:
                                   f"single-source DOBFS, policy {args.policy}, degree relabel {args.reindex}",
                       "scale": args.scale, "edgefactor": args.edgefactor, "n": n, "m": m,
                       "roots": args.roots, "policy": args.policy, "reindex": reindex,
-                      "params": overrides},
+                      "params": {k: getattr(params, k) for k in autotune.SPACE},
+                      "tuned_from": (os.path.relpath(autotune.tuned_path(args.scale, args.edgefactor), ROOT)
+                                     if tuned else None),
+                      "overrides": overrides},
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
-    dg.free()
-    g.free()
     return 0
 
 

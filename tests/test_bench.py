@@ -38,19 +38,48 @@ def test_traffic_from_counters(tmp_path):
     probe = "void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctorOnSelf_add<int>>(int)"
     td = "dobfs::(anonymous namespace)::k_level_td(dobfs::GView, dobfs::WView, dobfs::KParams)"
     bu = "dobfs::(anonymous namespace)::k_level_bu(dobfs::GView, dobfs::WView, dobfs::KParams)"
-    other = "dobfs::(anonymous namespace)::k_finalize(dobfs::GView, dobfs::WView, int)"
+    fin = "dobfs::(anonymous namespace)::k_finalize(dobfs::GView, dobfs::WView, int)"
+    other = "dobfs::(anonymous namespace)::k_init_fill(dobfs::GView, dobfs::WView)"
     # a 1 MiB probe reads as 512 KiB fetched and 1024 KiB written: factors 2 and 1
     _csv(tmp_path / "f.csv", "FETCH_SIZE", [(probe, 512.0), (td, 10.0), (bu, 30.0), (other, 999.0), (td, 0.0),
-                                            (bu, 20.0)])
-    _csv(tmp_path / "w.csv", "WRITE_SIZE", [(probe, 1024.0), (td, 4.0), (bu, 6.0), (td, 0.0), (bu, 10.0)])
+                                            (bu, 20.0), (fin, 7.0)])
+    _csv(tmp_path / "w.csv", "WRITE_SIZE", [(probe, 1024.0), (td, 4.0), (bu, 6.0), (td, 0.0), (bu, 10.0),
+                                            (fin, 3.0)])
     out = tmp_path / "traffic.json"
     ent = bench.traffic_from_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 1 << 20, "k", str(out))
-    assert ent["launches"] == 2
     assert ent["fetch_factor"] == pytest.approx(2.0) and ent["write_factor"] == pytest.approx(1.0)
-    assert ent["fetch_bytes_per_launch"] == round(60 * 1024 * 2 / 2)
-    assert ent["write_bytes_per_launch"] == round(20 * 1024 / 2)
-    assert ent["bytes_per_launch"] == ent["fetch_bytes_per_launch"] + ent["write_bytes_per_launch"]
+    bu_ent = ent["kernels"]["k_level_bu"]
+    assert bu_ent["launches"] == 2
+    assert bu_ent["fetch_bytes_per_launch"] == round(50 * 1024 * 2 / 2)
+    assert bu_ent["write_bytes_per_launch"] == round(16 * 1024 / 2)
+    assert bu_ent["bytes_per_launch"] == bu_ent["fetch_bytes_per_launch"] + bu_ent["write_bytes_per_launch"]
+    td_ent = ent["kernels"]["k_level_td"]
+    assert td_ent["bytes_per_launch"] == round(10 * 1024 * 2 / 2) + round(4 * 1024 / 2)
+    assert ent["kernels"]["k_finalize"]["launches"] == 1
+    assert "k_aux" not in ent["kernels"]  # no dispatches of it in these files
     assert json.loads(out.read_text())["k"]["source_sha256"] == bench.kernel_source_digest()
+
+
+def test_level_bytes_and_conversions():
+    bu = {"dir": 1, "n_f": 5, "m_f": 50, "scanned": 100, "checked": 80, "found": 10}
+    assert bench.bottom_up_bytes(bu, 4) == 16 * 4 + 8 * 100 + 4.125 * 80 + 8 * 10
+    td = {"dir": 0, "n_f": 3, "m_f": 70_000, "scanned": 0, "checked": 30, "found": 7}
+    assert bench.top_down_bytes(td) == 20 * 3 + 4.125 * 30 + 28.25 * 7
+    small_td = dict(td, m_f=100)
+    # level 0 never converts; after a bottom-up level, or a large top-down
+    # level, the bitmap is turned into a queue; after a small top-down level
+    # the queue is handed on as is
+    assert bench.to_queue_bytes([td], 0, 4) == 0.0
+    assert bench.to_queue_bytes([bu, td], 1, 4) == 16 * 4 + 4 * 3
+    assert bench.to_queue_bytes([td, td], 1, 4) == 16 * 4 + 4 * 3
+    assert bench.to_queue_bytes([small_td, td], 1, 4) == 0.0
+    assert bench.to_queue_bytes([td, bu], 1, 4) == 0.0
+
+
+def test_host_spec():
+    spec = bench.host_spec()
+    assert spec["nproc"] >= 1 and spec["cpus_allowed"] >= 1
+    assert isinstance(spec["cpu_model"], str)
 
 
 def test_source_digest_ignores_comments_only(tmp_path, monkeypatch):
