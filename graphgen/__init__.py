@@ -282,6 +282,10 @@ def _load_device():
     lib.ggd_kronecker.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int,
                                   P(ctypes.c_void_p), P(ctypes.c_void_p), P(ctypes.c_int64), P(ctypes.c_int64),
                                   ctypes.c_void_p]
+    lib.ggd_chung_lu.restype = ctypes.c_int
+    lib.ggd_chung_lu.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.c_uint64, P(ctypes.c_void_p), P(ctypes.c_void_p),
+                                 P(ctypes.c_int64), P(ctypes.c_int64), ctypes.c_void_p]
     lib.ggd_free.restype = None
     lib.ggd_free.argtypes = [ctypes.c_void_p]
     lib.ggd_last_error.restype = ctypes.c_char_p
@@ -356,6 +360,24 @@ def kronecker_device(scale: int, edgefactor: int = KRON_EDGEFACTOR, seed: int = 
     if rc:
         raise RuntimeError(f"graphgen device builder failed ({rc}): {lib.ggd_last_error().decode()}")
     return DeviceCSR(off.value, idx.value, n.value, m.value, f"kron-s{scale}-ef{edgefactor}-seed{seed}")
+
+
+def chung_lu_device(n_core: int, gamma: float = 2.2, avg_deg: float = 20.0, max_deg: float = 1e6,
+                    n_tails: int = 50, tail_len: int = 200, seed: int = 3, stream=None) -> DeviceCSR:
+    """Same graph as :func:`chung_lu`, built on the current GPU (the alias
+    table and the tail anchors on the host, every edge on the device)."""
+    import torch
+    lib = _load_device()
+    off, idx = ctypes.c_void_p(), ctypes.c_void_p()
+    n, m = ctypes.c_int64(0), ctypes.c_int64(0)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib.ggd_chung_lu(int(n_core), float(gamma), float(avg_deg), float(max_deg), int(n_tails), int(tail_len),
+                          int(seed), ctypes.byref(off), ctypes.byref(idx), ctypes.byref(n), ctypes.byref(m),
+                          ctypes.c_void_p(int(s.cuda_stream)))
+    if rc:
+        raise RuntimeError(f"device Chung-Lu builder failed ({rc}): {lib.ggd_last_error().decode()}")
+    return DeviceCSR(off.value, idx.value, n.value, m.value,
+                     f"cl-n{n_core}-g{gamma}-d{avg_deg}-t{n_tails}x{tail_len}-seed{seed}")
 
 
 def sample_roots_device(g: DeviceCSR, count: int, seed: int) -> np.ndarray:

@@ -28,6 +28,7 @@
 
 #include <omp.h>
 
+#include "gg_chunglu.h"
 #include "gg_rng.h"
 
 namespace {
@@ -149,19 +150,6 @@ gg_rmat_t rmat_thresholds(double a, double b, double c) {
 
 /* Keyed bijection of [0, n) for arbitrary n >= 1 (cycle walking over the
    power-of-two Feistel permutation). */
-uint32_t permute_n(uint64_t key, int bits, uint64_t n, uint32_t x) {
-  const int h = (bits + 1) >> 1;
-  uint32_t y = gg_feistel(key, h, x);
-  while ((uint64_t)y >= n) y = gg_feistel(key, h, y);
-  return y;
-}
-
-int bits_for(uint64_t n) {
-  int b = 1;
-  while ((1ull << b) < n) ++b;
-  return b;
-}
-
 }  // namespace
 
 extern "C" {
@@ -232,39 +220,10 @@ gg_csr* gg_kronecker(int scale, int edgefactor, uint64_t seed, double a, double 
   return g;
 }
 
-/* Expected-degree weights of the Chung-Lu family: w_i = c (i0 + i)^(-p),
-   p = 1/(gamma-1), with i0 and c solved so that w_0 = max_deg and the mean
-   weight is avg_deg.  Returns 0 on success. */
+/* Expected-degree weights of the Chung-Lu family (gg_chunglu.h). */
 int gg_chung_lu_weights(int64_t n, double gamma, double avg_deg, double max_deg, double* i0_out,
                         double* c_out) {
-  if (n < 2 || gamma <= 1.0 || avg_deg <= 0 || max_deg <= avg_deg) return -1;
-  const double p = 1.0 / (gamma - 1.0);
-  /* mean(i0) = (max_deg * i0^p / n) * sum_i (i0+i)^(-p), increasing in i0.
-     The sum is exact over its first K terms and the midpoint-rule integral
-     beyond (relative error far below 1e-9 for K = 1e5). */
-  const int64_t K = std::min<int64_t>(n, 100000);
-  auto mean_for = [&](double i0) {
-    double s = 0.0;
-    for (int64_t i = 0; i < K; ++i) s += std::pow(i0 + (double)i, -p);
-    if (K < n) {
-      const double a = i0 + (double)K - 0.5, b = i0 + (double)n - 0.5;
-      s += (std::pow(b, 1.0 - p) - std::pow(a, 1.0 - p)) / (1.0 - p);
-    }
-    return max_deg * std::pow(i0, p) * s / (double)n;
-  };
-  double lo = 1e-9, hi = 1.0;
-  while (mean_for(hi) < avg_deg) {
-    hi *= 2.0;
-    if (hi > 1e18) return -2;
-  }
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mean_for(mid) < avg_deg) lo = mid; else hi = mid;
-    if (hi - lo <= 1e-12 * hi) break;
-  }
-  *i0_out = 0.5 * (lo + hi);
-  *c_out = max_deg * std::pow(*i0_out, p);
-  return 0;
+  return gg_cl_weights(n, gamma, avg_deg, max_deg, i0_out, c_out);
 }
 
 /* Chung-Lu core of n_core vertices plus n_tails path tails of tail_len new
@@ -278,92 +237,43 @@ gg_csr* gg_chung_lu(int64_t n_core, double gamma, double avg_deg, double max_deg
   const int64_t n = n_core + (int64_t)n_tails * tail_len;
   if (n > 2147483647LL) return nullptr;
   double i0, c;
-  if (gg_chung_lu_weights(n_core, gamma, avg_deg, max_deg, &i0, &c)) return nullptr;
-  const double p = 1.0 / (gamma - 1.0);
-
-  /* Walker/Vose alias table over the weights, thresholds quantised to 32 bits. */
-  std::vector<double> w((size_t)n_core);
-  double total = 0.0;
-  for (int64_t i = 0; i < n_core; ++i) {
-    w[(size_t)i] = c * std::pow(i0 + (double)i, -p);
-    total += w[(size_t)i];
-  }
-  std::vector<uint32_t> thr((size_t)n_core);
-  std::vector<int32_t> alias((size_t)n_core);
-  {
-    std::vector<double> q((size_t)n_core);
-    std::vector<int64_t> small, large;
-    small.reserve((size_t)n_core);
-    large.reserve((size_t)n_core);
-    for (int64_t i = 0; i < n_core; ++i) {
-      q[(size_t)i] = w[(size_t)i] * (double)n_core / total;
-      (q[(size_t)i] < 1.0 ? small : large).push_back(i);
-    }
-    while (!small.empty() && !large.empty()) {
-      const int64_t s = small.back(); small.pop_back();
-      const int64_t l = large.back();
-      const double qs = q[(size_t)s];
-      thr[(size_t)s] = (uint32_t)std::min(4294967295.0, std::floor(qs * 4294967296.0));
-      alias[(size_t)s] = (int32_t)l;
-      q[(size_t)l] = (q[(size_t)l] + qs) - 1.0;
-      if (q[(size_t)l] < 1.0) { large.pop_back(); small.push_back(l); }
-    }
-    for (int64_t i : large) { thr[(size_t)i] = 0xFFFFFFFFu; alias[(size_t)i] = (int32_t)i; }
-    for (int64_t i : small) { thr[(size_t)i] = 0xFFFFFFFFu; alias[(size_t)i] = (int32_t)i; }
-  }
-
-  const uint64_t key = gg_stream_key(seed, GG_STREAM_CL_EDGES);
-  const uint64_t pkey = gg_stream_key(seed, GG_STREAM_PERM);
-  const uint64_t tkey = gg_stream_key(seed, GG_STREAM_CL_TAILS);
-  const int pbits = bits_for((uint64_t)n_core);
+  if (gg_cl_weights(n_core, gamma, avg_deg, max_deg, &i0, &c)) return nullptr;
+  std::vector<uint32_t> thr;
+  std::vector<int32_t> alias;
+  gg_cl_alias(n_core, i0, c, 1.0 / (gamma - 1.0), thr, alias);
+  gg_cl_core_t t;
+  t.key = gg_stream_key(seed, GG_STREAM_CL_EDGES);
+  t.pkey = gg_stream_key(seed, GG_STREAM_PERM);
+  t.n_core = n_core;
+  t.pbits = gg_bits_for((uint64_t)n_core);
+  t.pad = 0;
+  t.thr = thr.data();
+  t.alias = alias.data();
   const int64_t m_core = (int64_t)std::llround((double)n_core * avg_deg / 2.0);
-  const uint32_t* thr_p = thr.data();
-  const int32_t* alias_p = alias.data();
-  auto endpoint = [&](uint64_t x_slot, uint64_t x_coin) -> uint32_t {
-    const uint64_t s = gg_below(x_slot, (uint64_t)n_core);
-    const uint32_t pick = ((uint32_t)x_coin < thr_p[s]) ? (uint32_t)s : (uint32_t)alias_p[s];
-    return permute_n(pkey, pbits, (uint64_t)n_core, pick);
-  };
-  auto core_edge = [&](int64_t k, uint32_t& u, uint32_t& v) {
-    const uint64_t base = (uint64_t)k * 4ull;
-    u = endpoint(gg_draw(key, base + 0), gg_draw(key, base + 1));
-    v = endpoint(gg_draw(key, base + 2), gg_draw(key, base + 3));
-  };
 
   /* Tail anchors: uniform core vertices of degree >= 1 in the core graph
      (degree counted before de-duplication: a non-loop edge survives it). */
-  std::vector<uint32_t> anchor((size_t)n_tails);
+  std::vector<uint32_t> anchor((size_t)std::max<int32_t>(n_tails, 1));
   if (n_tails > 0 && tail_len > 0) {
     std::vector<uint8_t> has_edge((size_t)n_core, 0);
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < m_core; ++k) {
       uint32_t u, v;
-      core_edge(k, u, v);
+      gg_cl_core_edge(t, k, &u, &v);
       if (u != v) {
         __atomic_store_n(&has_edge[u], (uint8_t)1, __ATOMIC_RELAXED);
         __atomic_store_n(&has_edge[v], (uint8_t)1, __ATOMIC_RELAXED);
       }
     }
-    uint64_t ctr = 0;
-    for (int32_t t = 0; t < n_tails; ++t) {
-      for (;;) {
-        const uint64_t cand = gg_below(gg_draw(tkey, ctr++), (uint64_t)n_core);
-        if (has_edge[(size_t)cand]) { anchor[(size_t)t] = (uint32_t)cand; break; }
-        if (ctr > (uint64_t)n_core * 64ull + 4096ull) { *status = -2; return nullptr; }
-      }
+    if (gg_cl_anchors(n_core, seed, n_tails, has_edge.data(), anchor.data())) {
+      *status = -2;
+      return nullptr;
     }
   }
   const uint32_t* anchor_p = anchor.data();
   const int64_t per_tail = tail_len;
-  const int64_t count = m_core + (int64_t)n_tails * per_tail;
-  auto edge = [&](int64_t k, uint32_t& u, uint32_t& v) {
-    if (k < m_core) { core_edge(k, u, v); return; }
-    const int64_t r = k - m_core;
-    const int64_t t = r / per_tail, j = r % per_tail;
-    const uint32_t first = (uint32_t)(n_core + t * per_tail);
-    if (j == 0) { u = anchor_p[t]; v = first; }
-    else { u = first + (uint32_t)(j - 1); v = first + (uint32_t)j; }
-  };
+  const int64_t count = m_core + (tail_len > 0 ? (int64_t)n_tails * per_tail : 0);
+  auto edge = [&](int64_t k, uint32_t& u, uint32_t& v) { gg_cl_edge(t, m_core, anchor_p, per_tail, k, &u, &v); };
   Csr csr;
   *status = build_csr(n, count, edge, &csr);
   if (*status) return nullptr;

@@ -1,6 +1,7 @@
 /*
- * Device builder of the seeded Kronecker graphs, for sizes the host builder
- * cannot hold (up to scale 30: ~34 billion directed entries).
+ * Device builder of the seeded Kronecker and Chung-Lu graphs, for sizes the
+ * host builder cannot hold or builds slowly (Kronecker up to scale 30: ~34
+ * billion directed entries; Chung-Lu with 100M core vertices).
  *
  * Produces exactly the CSR of the host builder (gg_cpu.cpp) for the same
  * parameters: the same counter-based edge stream (gg_rng.h), self-loops
@@ -33,6 +34,7 @@
 #include <string>
 #include <vector>
 
+#include "gg_chunglu.h"
 #include "gg_rng.h"
 
 namespace {
@@ -68,28 +70,58 @@ __device__ __forceinline__ void kron_edge(const KronParams& p, uint64_t k, uint3
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_count(KronParams p, int64_t count, uint32_t* cnt) {
+/* Edge generators: edge k of the stream, both endpoints. */
+struct KronGen {
+  KronParams p;
+  __device__ __forceinline__ void edge(uint64_t k, uint32_t& u, uint32_t& v) const { kron_edge(p, k, u, v); }
+};
+
+struct ClGen {
+  gg_cl_core_t t;       /* alias table in device memory */
+  int64_t m_core;
+  const uint32_t* anchor;
+  int64_t tail_len;
+  __device__ __forceinline__ void edge(uint64_t k, uint32_t& u, uint32_t& v) const {
+    gg_cl_edge(t, m_core, anchor, tail_len, (int64_t)k, &u, &v);
+  }
+};
+
+template <class Gen>
+__global__ void __launch_bounds__(kBlock) k_count(Gen gen, int64_t count, uint32_t* cnt) {
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += nth) {
     uint32_t u, v;
-    kron_edge(p, (uint64_t)k, u, v);
+    gen.edge((uint64_t)k, u, v);
     if (u == v) continue;
     atomicAdd(&cnt[u], 1u);
     atomicAdd(&cnt[v], 1u);
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_fill(KronParams p, int64_t count, uint32_t* cur, const int64_t* off,
+template <class Gen>
+__global__ void __launch_bounds__(kBlock) k_fill(Gen gen, int64_t count, uint32_t* cur, const int64_t* off,
                                                int32_t* idx) {
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += nth) {
     uint32_t u, v;
-    kron_edge(p, (uint64_t)k, u, v);
+    gen.edge((uint64_t)k, u, v);
     if (u == v) continue;
     const uint32_t pu = atomicAdd(&cur[u], 1u);
     const uint32_t pv = atomicAdd(&cur[v], 1u);
     idx[off[u] + pu] = (int32_t)v;
     idx[off[v] + pv] = (int32_t)u;
+  }
+}
+
+/* Chung-Lu: marks the core vertices with a non-loop generated edge. */
+__global__ void __launch_bounds__(kBlock) k_cl_marks(gg_cl_core_t t, int64_t m_core, uint8_t* has_edge) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m_core; k += nth) {
+    uint32_t u, v;
+    gg_cl_core_edge(t, k, &u, &v);
+    if (u == v) continue;
+    has_edge[u] = 1;
+    has_edge[v] = 1;
   }
 }
 
@@ -207,8 +239,10 @@ int batch_bounds(const int64_t* off, int64_t n, int64_t total, int64_t step, std
   return 0;
 }
 
-int build_kronecker(const KronParams& p, int64_t n, int64_t count, int64_t** out_off, int32_t** out_idx,
-                    int64_t* out_m, hipStream_t s) {
+/* The CSR of `count` generated edges over n vertices (IDs below 2^bits). */
+template <class Gen>
+int build_csr_dev(const Gen& gen, int64_t n, int64_t count, int bits, int64_t** out_off, int32_t** out_idx,
+                  int64_t* out_m, hipStream_t s) {
   uint32_t* cnt = nullptr;
   int64_t* off_dup = nullptr;
   int64_t* off = nullptr;
@@ -238,14 +272,14 @@ int build_kronecker(const KronParams& p, int64_t n, int64_t count, int64_t** out
   GG_TRY(hipMalloc(&cnt, sizeof(uint32_t) * (size_t)(n + 1)), "counts");
   GG_TRY(hipMalloc(&off_dup, sizeof(int64_t) * (size_t)(n + 1)), "offsets");
   GG_TRY(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (size_t)(n + 1), s), "memset");
-  hipLaunchKernelGGL(k_count, dim3(grid_for(count)), dim3(kBlock), 0, s, p, count, cnt);
+  hipLaunchKernelGGL(k_count<Gen>, dim3(grid_for(count)), dim3(kBlock), 0, s, gen, count, cnt);
   GG_TRY(hipGetLastError(), "count");
   if ((rc = scan_counts(cnt, n, off_dup, s))) return cleanup(rc);
   int64_t m_dup = 0;
   GG_TRY(hipMemcpy(&m_dup, off_dup + n, sizeof(int64_t), hipMemcpyDeviceToHost), "m_dup");
   GG_TRY(hipMalloc(&idx, sizeof(int32_t) * (size_t)(m_dup > 0 ? m_dup : 1)), "indices");
   GG_TRY(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (size_t)(n + 1), s), "memset");
-  hipLaunchKernelGGL(k_fill, dim3(grid_for(count)), dim3(kBlock), 0, s, p, count, cnt, off_dup, idx);
+  hipLaunchKernelGGL(k_fill<Gen>, dim3(grid_for(count)), dim3(kBlock), 0, s, gen, count, cnt, off_dup, idx);
   GG_TRY(hipGetLastError(), "fill");
 
   /* 4. sort + de-duplicate in batches of whole rows. */
@@ -266,7 +300,6 @@ int build_kronecker(const KronParams& p, int64_t n, int64_t count, int64_t** out
   GG_TRY(hipMalloc(&rel, sizeof(uint32_t) * (size_t)(max_rows + 1)), "relative offsets");
   size_t sort_bytes = 0;
   {
-    const int bits = p.scale;
     GG_TRY(rocprim::segmented_radix_sort_keys(nullptr, sort_bytes, reinterpret_cast<uint32_t*>(idx),
                                               reinterpret_cast<uint32_t*>(tmp), (unsigned int)max_batch,
                                               (unsigned int)max_rows, rel, rel + 1, 0, bits, s),
@@ -349,7 +382,82 @@ int ggd_kronecker(int scale, int edgefactor, uint64_t seed, const uint32_t thres
   const int64_t n = (int64_t)1 << scale;
   const int64_t count = (int64_t)edgefactor << scale;
   *n_out = n;
-  return build_kronecker(p, n, count, offsets, indices, m_out, reinterpret_cast<hipStream_t>(stream));
+  KronGen gen;
+  gen.p = p;
+  return build_csr_dev(gen, n, count, scale, offsets, indices, m_out, reinterpret_cast<hipStream_t>(stream));
+}
+
+/* Chung-Lu graph with path tails built on the current device: the graph of
+   the host builder's gg_chung_lu for the same arguments.  The alias table
+   and the tail anchors are computed on the host (sequential, as there);
+   the marks that the anchors need and every edge are generated on the
+   device.  Outputs and status as for ggd_kronecker (-2: no anchor). */
+int ggd_chung_lu(int64_t n_core, double gamma, double avg_deg, double max_deg, int32_t n_tails, int32_t tail_len,
+                 uint64_t seed, int64_t** offsets, int32_t** indices, int64_t* n_out, int64_t* m_out, void* stream) {
+  g_err.clear();
+  if (n_core < 2 || n_tails < 0 || tail_len < 0 || !offsets || !indices || !n_out || !m_out) return -1;
+  const int64_t n = n_core + (int64_t)n_tails * tail_len;
+  if (n > 2147483647LL) return -1;
+  double i0, c;
+  if (gg_cl_weights(n_core, gamma, avg_deg, max_deg, &i0, &c)) return -1;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<uint32_t> thr;
+  std::vector<int32_t> alias;
+  gg_cl_alias(n_core, i0, c, 1.0 / (gamma - 1.0), thr, alias);
+  const int64_t m_core = (int64_t)std::llround((double)n_core * avg_deg / 2.0);
+  uint32_t* d_thr = nullptr;
+  int32_t* d_alias = nullptr;
+  uint32_t* d_anchor = nullptr;
+  uint8_t* d_marks = nullptr;
+  auto done = [&](int status) {
+    (void)hipFree(d_thr);
+    (void)hipFree(d_alias);
+    (void)hipFree(d_anchor);
+    (void)hipFree(d_marks);
+    return status;
+  };
+#define GG_TRY(call, what)                                     \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) return done(fail(what, e_));         \
+  } while (0)
+  GG_TRY(hipMalloc(&d_thr, sizeof(uint32_t) * (size_t)n_core), "alias table");
+  GG_TRY(hipMalloc(&d_alias, sizeof(int32_t) * (size_t)n_core), "alias table");
+  GG_TRY(hipMemcpyAsync(d_thr, thr.data(), sizeof(uint32_t) * (size_t)n_core, hipMemcpyHostToDevice, s), "table copy");
+  GG_TRY(hipMemcpyAsync(d_alias, alias.data(), sizeof(int32_t) * (size_t)n_core, hipMemcpyHostToDevice, s),
+         "table copy");
+  gg_cl_core_t t;
+  t.key = gg_stream_key(seed, GG_STREAM_CL_EDGES);
+  t.pkey = gg_stream_key(seed, GG_STREAM_PERM);
+  t.n_core = n_core;
+  t.pbits = gg_bits_for((uint64_t)n_core);
+  t.pad = 0;
+  t.thr = d_thr;
+  t.alias = d_alias;
+  std::vector<uint32_t> anchor((size_t)std::max<int32_t>(n_tails, 1), 0u);
+  if (n_tails > 0 && tail_len > 0) {
+    GG_TRY(hipMalloc(&d_marks, (size_t)n_core), "marks");
+    GG_TRY(hipMemsetAsync(d_marks, 0, (size_t)n_core, s), "marks");
+    hipLaunchKernelGGL(k_cl_marks, dim3(grid_for(m_core)), dim3(kBlock), 0, s, t, m_core, d_marks);
+    GG_TRY(hipGetLastError(), "marks");
+    std::vector<uint8_t> marks((size_t)n_core);
+    GG_TRY(hipMemcpyAsync(marks.data(), d_marks, (size_t)n_core, hipMemcpyDeviceToHost, s), "marks copy");
+    GG_TRY(hipStreamSynchronize(s), "marks");
+    if (gg_cl_anchors(n_core, seed, n_tails, marks.data(), anchor.data())) return done(-2);
+  }
+  GG_TRY(hipMalloc(&d_anchor, sizeof(uint32_t) * anchor.size()), "anchors");
+  GG_TRY(hipMemcpyAsync(d_anchor, anchor.data(), sizeof(uint32_t) * anchor.size(), hipMemcpyHostToDevice, s),
+         "anchors");
+  GG_TRY(hipStreamSynchronize(s), "anchors");
+#undef GG_TRY
+  ClGen gen;
+  gen.t = t;
+  gen.m_core = m_core;
+  gen.anchor = d_anchor;
+  gen.tail_len = tail_len;
+  const int64_t count = m_core + (tail_len > 0 ? (int64_t)n_tails * tail_len : 0);
+  *n_out = n;
+  return done(build_csr_dev(gen, n, count, gg_bits_for((uint64_t)n), offsets, indices, m_out, s));
 }
 
 void ggd_free(void* p) {

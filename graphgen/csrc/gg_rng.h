@@ -107,4 +107,21 @@ GG_FN uint32_t gg_permute(uint64_t key, int scale, uint32_t x) {
   return y;
 }
 
+/* Keyed bijection of [0, n) for n <= 2^bits (bits = gg_bits_for(n)): the
+   Feistel network of gg_permute on 2*ceil(bits/2) bits, cycle-walked into
+   [0, n). */
+GG_FN uint32_t gg_permute_n(uint64_t key, int bits, uint64_t n, uint32_t x) {
+  const int h = (bits + 1) >> 1;
+  uint32_t y = gg_feistel(key, h, x);
+  while ((uint64_t)y >= n) y = gg_feistel(key, h, y);
+  return y;
+}
+
+/* Smallest b >= 1 with 2^b >= n. */
+GG_FN int gg_bits_for(uint64_t n) {
+  int b = 1;
+  while ((1ull << b) < n) ++b;
+  return b;
+}
+
 #endif /* GG_RNG_H */
