@@ -89,3 +89,57 @@ def test_other_component_marked_reached_is_rejected():
     p[5:] = [0, 5, 6, 7]
     got = bfs_tree_violations(*_t(g, d, p), 0)
     assert "parent-edge" in got
+
+
+# ---- depth-only checker (batched outputs) -----------------------------------
+
+def _td(g, d):
+    import torch
+    return (torch.from_numpy(g.offsets.astype(np.int64)), torch.from_numpy(g.indices.astype(np.int32)),
+            torch.from_numpy(d.astype(np.int32)))
+
+
+@pytest.mark.parametrize("gi", range(len(GRAPHS)))
+@pytest.mark.parametrize("chunk", [7, 1000, 1 << 27])
+def test_depth_checker_accepts_oracle(gi, chunk):
+    from tree_props import bfs_depth_violations
+    g = GRAPHS[gi]
+    for r in (0, g.n // 2, g.n - 1):
+        d, _ = oracle.bfs(g.offsets, g.indices, r)
+        assert bfs_depth_violations(*_td(g, d), r, chunk=chunk) == []
+
+
+def test_depth_checker_rejects_planted_mistakes():
+    from tree_props import bfs_depth_violations
+    g = GRAPHS[0]
+    root = int(gg.sample_roots(g, 1, seed=1)[0])
+    d0, _ = oracle.bfs(g.offsets, g.indices, root)
+
+    def check(d, expect):
+        got = bfs_depth_violations(*_td(g, d), root, chunk=5000)
+        assert expect in got, (expect, got)
+
+    d = d0.copy(); d[root] = 1
+    check(d, "root")
+    far = int(np.flatnonzero(d0 == d0.max())[0])
+    d = d0.copy(); d[far] += 1           # one level too deep: an edge spans 2
+    check(d, "edge-span")
+    d = d0.copy(); d[far] = -1           # a reached vertex left unreached
+    check(d, "edge-reach")
+    # a second depth-0 vertex and its whole component shifted one level
+    # shallower: every edge still spans at most 1, but the fake root has no
+    # neighbour of depth -1
+    d = d0.copy()
+    v = int(np.flatnonzero(d0 == 1)[0])
+    d[v] = 0
+    check(d, "no-parent")
+    # all depths off by the same amount except the root: spans stay <= 1
+    d = np.where(d0 > 0, d0 + 1, d0).astype(np.int32)
+    check(d, "no-parent")
+
+
+def test_depth_checker_on_path_fake_root():
+    from tree_props import bfs_depth_violations
+    g = gg.path(3)
+    d = np.array([0, 0, 1], dtype=np.int32)  # vertex 1 claims depth 0 beside the root
+    assert "no-parent" in bfs_depth_violations(*_td(g, d), 0)
