@@ -20,7 +20,7 @@ Other modes (--mode), each printing one JSON line of its own:
   chunglu  Chung-Lu power-law graph standing in for a real-world graph:
          100M core vertices, exponent 2.2, mean degree 20, max 10^6, plus 50
          path tails of 200 vertices (hundreds of levels, several direction
-         switches), built on the host; 16 roots, harmonic-mean GTEPS.
+         switches), built on the device; 16 roots, harmonic-mean GTEPS.
   serve  8 resident Kronecker graphs (scales 18, 20, 22, 24, 24, 25, 26, 26),
          Poisson arrivals of (graph, root) queries at several rates, served
          with continuous batching and, as the baseline, one plain run at a
@@ -320,16 +320,18 @@ def bench_chunglu(args) -> dict:
     import paper_1503_04359_amd as dobfs
     n_core, seed = args.cl_core, 3
     t0 = time.time()
-    g = gg.chung_lu(n_core, gamma=2.2, avg_deg=20.0, max_deg=1e6, n_tails=50, tail_len=200, seed=seed)
-    log(f"[chunglu] host-built in {time.time() - t0:.1f}s (n={g.n}, m={g.m}, max degree {int(g.degrees().max())})")
-    roots = gg.sample_roots(g, args.roots, seed=seed + 1_000_000)
+    g = gg.chung_lu_device(n_core, gamma=2.2, avg_deg=20.0, max_deg=1e6, n_tails=50, tail_len=200, seed=seed)
+    log(f"[chunglu] built on the device in {time.time() - t0:.1f}s (n={g.n}, m={g.m})")
+    roots = gg.sample_roots_device(g, args.roots, seed=seed + 1_000_000)
     reindex = args.reindex == "on"
     t0 = time.time()
-    dg = dobfs.Graph.upload(g.offsets, g.indices, reindex=reindex)
+    dg = dobfs.Graph.from_device_pointers(g.offsets_ptr, g.indices_ptr, g.n, g.m, borrow=not reindex,
+                                          reindex=reindex)
     torch.cuda.synchronize()
     log(f"[chunglu] resident in {time.time() - t0:.1f}s")
     n, m = g.n, g.m
-    del g
+    if reindex:
+        g.free()
     stream = torch.cuda.current_stream()
     depth = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -357,6 +359,8 @@ def bench_chunglu(args) -> dict:
         log(f"[chunglu] root {r}: {lv} levels, {sw} direction switches, {ms:.2f} ms")
     log(f"[chunglu] {gteps:.1f} GTEPS harmonic mean")
     dg.free()
+    if not reindex:
+        g.free()
     return {"metric": "GTEPS (harmonic mean over roots), Chung-Lu power-law graph with path tails",
             "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": 1,
             "ms_per_step": round(sum(times) / args.steps, 3), "higher_is_better": True, "scaling": "weak",
