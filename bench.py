@@ -208,26 +208,38 @@ def bench_batch(args) -> dict:
         mc.append(st.m_c)
     dg.batch(roots, depth=out, params=params, stream=stream)
     torch.cuda.synchronize()
-    bt, st_ = [], []
+    eager = dobfs.make_params(args.policy, flags=dobfs.RUN_EAGER)
+    dg.batch(roots, depth=out, params=eager, stream=stream)
+    torch.cuda.synchronize()
+    bt, st_, et = [], [], []
     for _ in range(args.steps):
         ms, _ = _timed(stream, lambda: dg.batch(roots, depth=out, params=params, stream=stream))
         bt.append(ms)
+        ms, _ = _timed(stream, lambda: dg.batch(roots, depth=out, params=eager, stream=stream))
+        et.append(ms)
         ms_seq = 0.0
         for r in roots:
             t, _ = _timed(stream, lambda r=r: dg.run(int(r), depth=depth, want_parent=False, params=params,
                                                          stream=stream))
             ms_seq += t
         st_.append(ms_seq)
-    # the batch must agree with the single runs
+    # both forms of the batch must agree with the single runs: `out` holds
+    # the kernel-by-kernel batch (the loop's last), then the captured one
     for b in (0, 31, 63):
         dg.run(int(roots[b]), depth=depth, want_parent=False, params=params, stream=stream)
         torch.cuda.synchronize()
         if not torch.equal(depth, out[b]):
             raise RuntimeError(f"batched depths of slot {b} differ from the single-source run")
-    batch_ms, seq_ms = min(bt), min(st_)
+    dg.batch(roots, depth=out, params=params, stream=stream)
+    for b in (0, 31, 63):
+        dg.run(int(roots[b]), depth=depth, want_parent=False, params=params, stream=stream)
+        torch.cuda.synchronize()
+        if not torch.equal(depth, out[b]):
+            raise RuntimeError(f"batched depths of slot {b} (captured run) differ from the single-source run")
+    batch_ms, seq_ms, eager_ms = min(bt), min(st_), min(et)
     total_mc = float(sum(mc))
-    log(f"[batch] 64 roots: batched {batch_ms:.2f} ms, one at a time {seq_ms:.2f} ms "
-        f"({seq_ms / batch_ms:.2f}x)")
+    log(f"[batch] 64 roots: batched {batch_ms:.2f} ms as one captured graph ({eager_ms:.2f} ms launched kernel "
+        f"by kernel), one at a time {seq_ms:.2f} ms ({seq_ms / batch_ms:.2f}x)")
     dg.free()
     g.free()
     return {"metric": f"batched GTEPS, 64 roots in one pass, kronecker scale {scale}",
@@ -239,6 +251,7 @@ def bench_batch(args) -> dict:
                                    f"{args.reindex}, policy {args.policy}", "n": n, "m": g.m},
             "sequential": {"ms": round(seq_ms, 3), "value": round(total_mc / (seq_ms * 1e-3) / 1e9, 3),
                            "unit": "GTEPS"},
+            "eager_batch_ms": round(eager_ms, 3),
             "speedup_vs_sequential": round(seq_ms / batch_ms, 3)}
 
 
@@ -274,8 +287,14 @@ def bench_pack(args) -> dict:
     depth = torch.empty(max(g.n for g in gs), dtype=torch.int32, device="cuda")
     _, _, st = pk.run_pack(roots, depth=out, params=params, stats=True, stream=stream)
     total_mc = float(st.m_c)
-    pt, stimes = [], []
+    eager = dobfs.make_params(args.policy, flags=dobfs.RUN_EAGER)
+    pk.run_pack(roots, depth=out, params=eager, stream=stream)
+    pk.run_pack(roots, depth=out, params=params, stream=stream)
+    torch.cuda.synchronize()
+    pt, stimes, et = [], [], []
     for _ in range(args.steps):
+        ms, _ = _timed(stream, lambda: pk.run_pack(roots, depth=out, params=eager, stream=stream))
+        et.append(ms)
         ms, _ = _timed(stream, lambda: pk.run_pack(roots, depth=out, params=params, stream=stream))
         pt.append(ms)
 
@@ -291,9 +310,9 @@ def bench_pack(args) -> dict:
         lo = int(pk.bases[i])
         if not torch.equal(depth[:gs[i].n], out[lo:lo + gs[i].n]):
             raise RuntimeError(f"packed depths of graph {i} differ from its single-source run")
-    pack_ms, seq_ms = min(pt), min(stimes)
-    log(f"[pack] {count} graphs: one pass {pack_ms:.2f} ms, one at a time {seq_ms:.2f} ms "
-        f"({seq_ms / pack_ms:.2f}x)")
+    pack_ms, seq_ms, eager_ms = min(pt), min(stimes), min(et)
+    log(f"[pack] {count} graphs: one pass {pack_ms:.2f} ms as one captured graph ({eager_ms:.2f} ms launched "
+        f"kernel by kernel), one at a time {seq_ms:.2f} ms ({seq_ms / pack_ms:.2f}x)")
     for dg in singles:
         dg.free()
     pk.free()
@@ -309,6 +328,7 @@ def bench_pack(args) -> dict:
             "gteps": round(total_mc / (pack_ms * 1e-3) / 1e9, 3),
             "sequential": {"ms": round(seq_ms, 3), "value": round(count / (seq_ms * 1e-3), 1),
                            "unit": "graphs/s"},
+            "eager_pack_ms": round(eager_ms, 3),
             "speedup_vs_sequential": round(seq_ms / pack_ms, 3)}
 
 

@@ -68,6 +68,19 @@ typedef struct dobfs_graph_s* dobfs_graph_t; /* opaque, library-owned */
                                       HIP events on `stream`; the summed
                                       durations per kernel are reported in
                                       dobfs_stats                           */
+#define DOBFS_RUN_GRAPH 0x2u       /* run the traversal as one captured HIP
+                                      graph: init, 2 * chunk_levels level
+                                      slots and the finalize, recorded once
+                                      per workspace and replayed while the
+                                      arguments (graph, outputs, roots,
+                                      params) repeat; a traversal with more
+                                      levels continues with ordinary
+                                      launches.  The default of
+                                      dobfs_batch_submit and dobfs_pack_run;
+                                      for dobfs_run / dobfs_run_multi only on
+                                      request.  Excludes the two flags below
+                                      (EINVAL).                             */
+#define DOBFS_RUN_EAGER 0x4u       /* never use a captured graph             */
 
 /* ---- direction policies (Section 3.3) ------------------------------------ */
 #define DOBFS_POLICY_EDGE 0      /* top-down -> bottom-up when the next
@@ -206,7 +219,8 @@ int dobfs_run(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* parent, co
    pinned or library allocation and no events.  It checks for the end of the
    traversal after each chunk of levels with a stream synchronisation and
    returns once depth/parent are complete.  Arguments and results as for
-   dobfs_run, except that DOBFS_RUN_TIME_KERNELS is refused (EINVAL) and a
+   dobfs_run, except that DOBFS_RUN_TIME_KERNELS and DOBFS_RUN_GRAPH are
+   refused (EINVAL) and a
    relabelled graph uses its caller-ID column only if an earlier dobfs_run
    built it.  The array is shared by every call on the device and keeps the
    last call's contents (each call clears what it reads first); calls that

@@ -46,7 +46,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ---- status codes and flags (include/dobfs.h) ------------------------------
 OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 SRC_DEVICE, VALIDATE, VALIDATE_SYMMETRY, REINDEX_DEGREE, BORROW = 0x1, 0x2, 0x4, 0x8, 0x10
-RUN_TIME_KERNELS = 0x1
+RUN_TIME_KERNELS, RUN_GRAPH, RUN_EAGER = 0x1, 0x2, 0x4
 POLICY_EDGE, POLICY_PAPER, POLICY_FORCED_TD, POLICY_FORCED_BU, POLICY_RANDOM, POLICY_COST = 0, 1, 2, 3, 4, 5
 POLICIES = {"edge": POLICY_EDGE, "paper": POLICY_PAPER, "td": POLICY_FORCED_TD,
             "bu": POLICY_FORCED_BU, "random": POLICY_RANDOM, "cost": POLICY_COST}

@@ -73,8 +73,20 @@ struct Workspace {
   int32_t* roots_dev = nullptr;   /* multi-root runs */
   int64_t roots_cap = 0;
   bool busy = false;
+  /* captured runs: a traversal's launches recorded once as a HIP graph and
+     replayed while the arguments repeat (kind 0 single- and multi-source,
+     kind 1 batched) */
+  struct Captured {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  Captured cap[2];
+  hipStream_t cap_stream = nullptr;  /* capture only: nothing runs on it */
 
   void release() {
+    for (auto& c : cap)
+      if (c.exec) (void)hipGraphExecDestroy(c.exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     dfree(ms_visit); dfree(ms_cur0); dfree(ms_cur1); dfree(ms_nxt); dfree(ms_internal); dfree(roots_dev);
     dfree(vis); dfree(fr0); dfree(fr1); dfree(q0); dfree(qd0); dfree(qd1);
     dfree(huge_u); dfree(huge_base); dfree(parent_scratch); dfree(packed); dfree(ctl); dfree(log);
@@ -275,7 +287,10 @@ int check_params(const dobfs_params& p) {
   if (p.td_wave_cut < 0 || p.td_wave_cut > 4096 || p.td_huge_cut < 1 || p.bu_heavy_cut < 1)
     return fail(DOBFS_EINVAL, "degree cut-offs out of range");
   if (p.chunk_levels < 1 || p.chunk_levels > 1024) return fail(DOBFS_EINVAL, "chunk_levels out of range");
-  if (p.flags & ~DOBFS_RUN_TIME_KERNELS) return fail(DOBFS_EINVAL, "unknown run flag");
+  if (p.flags & ~(DOBFS_RUN_TIME_KERNELS | DOBFS_RUN_GRAPH | DOBFS_RUN_EAGER))
+    return fail(DOBFS_EINVAL, "unknown run flag");
+  if ((p.flags & DOBFS_RUN_GRAPH) && (p.flags & (DOBFS_RUN_EAGER | DOBFS_RUN_TIME_KERNELS)))
+    return fail(DOBFS_EINVAL, "DOBFS_RUN_GRAPH excludes DOBFS_RUN_EAGER and DOBFS_RUN_TIME_KERNELS");
   return DOBFS_OK;
 }
 
@@ -319,6 +334,64 @@ int level_loop(Workspace* w, const Ctl* ctl_dev, int K, int64_t max_levels, hipS
     if (w->done_host[c & 1]) break;
   }
   *enqueued = launches;
+  return DOBFS_OK;
+}
+
+/* Raw bytes of the arguments a captured run bakes in (the structs have no
+   implicit padding). */
+struct KeyBytes {
+  std::vector<unsigned char> b;
+  template <class T>
+  KeyBytes& add(const T& x) {
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(&x);
+    b.insert(b.end(), p, p + sizeof(T));
+    return *this;
+  }
+};
+
+/* The workspace's captured run of `kind` for these argument bytes: the
+   cached graph when the bytes repeat, otherwise `enqueue(stream)` recorded
+   on the workspace's capture stream and instantiated (nothing runs during
+   capture).  The workspace is exclusive to one run at a time and its
+   previous run has drained, so an old graph can be replaced. */
+template <class Enqueue>
+int captured_run(Workspace* w, int kind, const std::vector<unsigned char>& key, Enqueue enqueue,
+                 hipGraphExec_t* out) {
+  Workspace::Captured& c = w->cap[kind];
+  if (c.exec && c.key == key) {
+    *out = c.exec;
+    return DOBFS_OK;
+  }
+  if (!w->cap_stream)
+    DOBFS_HIP(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking), "capture stream");
+  DOBFS_HIP(hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal), "graph capture");
+  const int st = enqueue(w->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(w->cap_stream, &graph);
+  if (st != DOBFS_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st != DOBFS_OK ? st : fail(DOBFS_EDEVICE, "graph capture", e);
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return fail(DOBFS_EDEVICE, "graph instantiate", e2);
+  if (c.exec) (void)hipGraphExecDestroy(c.exec);
+  c.exec = exec;
+  c.key = key;
+  *out = exec;
+  return DOBFS_OK;
+}
+
+/* Launches a captured run on s and reports, after waiting for it, whether
+   the traversal ended within the run's level slots. */
+int launch_captured(Workspace* w, hipGraphExec_t exec, const Ctl* ctl_dev, hipStream_t s, bool* done) {
+  DOBFS_HIP(hipGraphLaunch(exec, s), "graph launch");
+  DOBFS_HIP(hipMemcpyAsync(&w->done_host[0], &ctl_dev->done, sizeof(int32_t), hipMemcpyDeviceToHost, s),
+            "done flag copy");
+  DOBFS_HIP(hipEventRecord(w->ev[0], s), "event record");
+  DOBFS_HIP(hipEventSynchronize(w->ev[0]), "captured run");
+  *done = w->done_host[0] != 0;
   return DOBFS_OK;
 }
 
@@ -652,7 +725,8 @@ int dobfs_graph_info(dobfs_graph_t g, dobfs_graph_info_t* info) {
 /* One traversal seeded from nroots roots (host caller IDs in roots), or
    from root when roots is NULL. */
 static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int64_t root, int32_t* depth,
-                     int32_t* parent, const dobfs_params* p, dobfs_stats* stats, void* stream) {
+                     int32_t* parent, const dobfs_params* p, dobfs_stats* stats, void* stream,
+                     bool graph_default = false) {
   g_last_error.clear();
   if (!g || !depth) return fail(DOBFS_EINVAL, "graph or depth is NULL");
   if (roots) {
@@ -731,10 +805,8 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
     DOBFS_HIP(hipStreamSynchronize(s), "roots copy");
     roots_dev = w->roots_dev;
   }
-  guard.launched = true;
-  DOBFS_HIP(launch_init(gv, wv, roots_dev, roots ? nroots : 1, root, first_direction(prm), g->grid, s),
-            "init launch");
   const bool timed = (prm.flags & DOBFS_RUN_TIME_KERNELS) != 0;
+  const bool graph = !timed && !(prm.flags & DOBFS_RUN_EAGER) && (graph_default || (prm.flags & DOBFS_RUN_GRAPH));
   /* timed runs bracket each of the slot's three kernels with events:
      tev[4i] k_level_td tev[4i+1] k_level_bu tev[4i+2] k_aux tev[4i+3] */
   auto level = [&](int64_t i) -> int {
@@ -758,11 +830,48 @@ static int run_multi(dobfs_graph_t g, const int64_t* roots, int32_t nroots, int6
     DOBFS_HIP(hipEventRecord(ev[3], s), "timing event");
     return DOBFS_OK;
   };
+  auto finalize = [&](hipStream_t cs) -> int {
+    if (g->new2old) {
+      DOBFS_HIP(launch_finalize(gv, wv, roots ? -1 : root, g->grid, cs), "finalize launch");
+      if (roots) DOBFS_HIP(launch_fix_roots(wv, roots_dev, nroots, cs), "root labels launch");
+    }
+    return DOBFS_OK;
+  };
   int64_t launches = 0;
-  if ((st = level_loop(w, w->ctl, prm.chunk_levels, g->n + 1, s, level, &launches)) != DOBFS_OK) return st;
-  if (g->new2old) {
-    DOBFS_HIP(launch_finalize(gv, wv, roots ? -1 : root, g->grid, s), "finalize launch");
-    if (roots) DOBFS_HIP(launch_fix_roots(wv, roots_dev, nroots, s), "root labels launch");
+  if (graph) {
+    /* one captured run: init, 2 * chunk_levels level slots and the
+       finalize; a traversal with more levels continues with ordinary
+       launches and maps its results again at the end */
+    const int K0 = 2 * prm.chunk_levels;
+    const int32_t first_dir = first_direction(prm);
+    auto enqueue = [&](hipStream_t cs) -> int {
+      DOBFS_HIP(launch_init(gv, wv, roots_dev, roots ? nroots : 1, root, first_dir, g->grid, cs), "init launch");
+      for (int i = 0; i < K0; ++i) {
+        DOBFS_HIP(launch_level(gv, wv, kp, g->grid, cs), "level launch");
+        DOBFS_HIP(launch_aux(gv, wv, kp, g->grid, cs), "aux launch");
+      }
+      return finalize(cs);
+    };
+    KeyBytes key;
+    key.add(gv).add(wv).add(kp).add(K0).add(root).add(nroots).add(roots_dev).add(first_dir);
+    hipGraphExec_t exec = nullptr;
+    if ((st = captured_run(w, 0, key.b, enqueue, &exec)) != DOBFS_OK) return st;
+    guard.launched = true;
+    bool done = false;
+    if ((st = launch_captured(w, exec, w->ctl, s, &done)) != DOBFS_OK) return st;
+    launches = K0;
+    if (!done) {
+      int64_t more = 0;
+      if ((st = level_loop(w, w->ctl, prm.chunk_levels, g->n + 1, s, level, &more)) != DOBFS_OK) return st;
+      launches += more;
+      if ((st = finalize(s)) != DOBFS_OK) return st;
+    }
+  } else {
+    guard.launched = true;
+    DOBFS_HIP(launch_init(gv, wv, roots_dev, roots ? nroots : 1, root, first_direction(prm), g->grid, s),
+              "init launch");
+    if ((st = level_loop(w, w->ctl, prm.chunk_levels, g->n + 1, s, level, &launches)) != DOBFS_OK) return st;
+    if ((st = finalize(s)) != DOBFS_OK) return st;
   }
   DOBFS_HIP(hipEventRecord(w->idle, s), "idle event");
   guard.launched = false;
@@ -799,8 +908,9 @@ int dobfs_run_noalloc(dobfs_graph_t g, int64_t root, int32_t* depth, int32_t* pa
   if (p) prm = *p; else dobfs_default_params(&prm);
   int st = check_params(prm);
   if (st != DOBFS_OK) return st;
-  if (prm.flags & DOBFS_RUN_TIME_KERNELS)
-    return fail(DOBFS_EINVAL, "DOBFS_RUN_TIME_KERNELS needs timing events, which the allocation-free run does not create");
+  if (prm.flags & (DOBFS_RUN_TIME_KERNELS | DOBFS_RUN_GRAPH))
+    return fail(DOBFS_EINVAL, "DOBFS_RUN_TIME_KERNELS and DOBFS_RUN_GRAPH need events or graphs, which the "
+                              "allocation-free run does not create");
   int dev = 0;
   DOBFS_HIP(hipGetDevice(&dev), "hipGetDevice");
   if (dev != g->device) return fail(DOBFS_EINVAL, "the graph is resident on another device");
@@ -907,15 +1017,46 @@ int dobfs_batch_submit(dobfs_graph_t g, const int64_t* roots, int32_t k, int32_t
   m.split_u = w->huge_u;
   m.split_base = w->huge_base;
   const KParams kp = to_kparams(prm);
-  guard.launched = true;
-  DOBFS_HIP(launch_ms_init(gv, m, r, first_direction(prm) == kDirBU ? 1 : 0, g->grid, s), "batch init launch");
+  const int32_t first_pull = first_direction(prm) == kDirBU ? 1 : 0;
   auto level = [&](int64_t) -> int {
     DOBFS_HIP(launch_ms_level(gv, m, kp, g->grid, s), "batch level launch");
     return DOBFS_OK;
   };
+  auto finalize = [&](hipStream_t cs) -> int {
+    if (g->new2old) DOBFS_HIP(launch_ms_finalize(gv, m, r, g->grid, cs), "batch finalize launch");
+    return DOBFS_OK;
+  };
   int64_t launches = 0;
-  if ((st = level_loop(w, w->ctl, prm.chunk_levels, g->n + 1, s, level, &launches)) != DOBFS_OK) return st;
-  if (g->new2old) DOBFS_HIP(launch_ms_finalize(gv, m, r, g->grid, s), "batch finalize launch");
+  if (!(prm.flags & (DOBFS_RUN_EAGER | DOBFS_RUN_TIME_KERNELS))) {
+    /* the whole batch as one captured run: init, 2 * chunk_levels level
+       slots (three kernels each) and the finalize; more levels continue
+       with ordinary launches, then the finalize runs again */
+    const int K0 = 2 * prm.chunk_levels;
+    auto enqueue = [&](hipStream_t cs) -> int {
+      DOBFS_HIP(launch_ms_init(gv, m, r, first_pull, g->grid, cs), "batch init launch");
+      for (int i = 0; i < K0; ++i) DOBFS_HIP(launch_ms_level(gv, m, kp, g->grid, cs), "batch level launch");
+      return finalize(cs);
+    };
+    KeyBytes key;
+    key.add(gv).add(m).add(kp).add(r).add(K0).add(first_pull);
+    hipGraphExec_t exec = nullptr;
+    if ((st = captured_run(w, 1, key.b, enqueue, &exec)) != DOBFS_OK) return st;
+    guard.launched = true;
+    bool done = false;
+    if ((st = launch_captured(w, exec, w->ctl, s, &done)) != DOBFS_OK) return st;
+    launches = K0;
+    if (!done) {
+      int64_t more = 0;
+      if ((st = level_loop(w, w->ctl, prm.chunk_levels, g->n + 1, s, level, &more)) != DOBFS_OK) return st;
+      launches += more;
+      if ((st = finalize(s)) != DOBFS_OK) return st;
+    }
+  } else {
+    guard.launched = true;
+    DOBFS_HIP(launch_ms_init(gv, m, r, first_pull, g->grid, s), "batch init launch");
+    if ((st = level_loop(w, w->ctl, prm.chunk_levels, g->n + 1, s, level, &launches)) != DOBFS_OK) return st;
+    if ((st = finalize(s)) != DOBFS_OK) return st;
+  }
   DOBFS_HIP(hipEventRecord(w->idle, s), "idle event");
   guard.launched = false;
   if (!stats) return DOBFS_OK;
@@ -993,7 +1134,7 @@ int dobfs_pack_run(dobfs_graph_t pack, const int64_t* roots, int32_t* depth, int
     if (roots[i] < 0 || lo + roots[i] >= hi) return fail(DOBFS_ERANGE, "root outside its graph");
     global[(size_t)i] = lo + roots[i];
   }
-  return run_multi(pack, global.data(), count, -1, depth, parent, p, stats, stream);
+  return run_multi(pack, global.data(), count, -1, depth, parent, p, stats, stream, /*graph_default=*/true);
 }
 
 static int session_view(dobfs_session_s* ss, MsView* m) {
