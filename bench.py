@@ -21,6 +21,9 @@ Other modes (--mode), each printing one JSON line of its own:
          100M core vertices, exponent 2.2, mean degree 20, max 10^6, plus 50
          path tails of 200 vertices (hundreds of levels, several direction
          switches), built on the device; 16 roots, harmonic-mean GTEPS.
+  energy MTEPS/W: the default workload's traversals back to back for a fixed
+         window while the GPU's socket power is sampled (Section 4.3's
+         energy case, for the GPU alone).
   serve  8 resident Kronecker graphs (scales 18, 20, 22, 24, 24, 25, 26, 26),
          Poisson arrivals of (graph, root) queries at several rates, served
          with continuous batching and, as the baseline, one plain run at a
@@ -491,6 +494,128 @@ def bench_serve(args) -> dict:
             "rates": results}
 
 
+def power_reader():
+    """(read() -> watts, source) for the GPU's socket power: the amdgpu
+    hwmon node's instantaneous power1_input (microwatts), else amd-smi."""
+    import glob
+    for path in sorted(glob.glob("/sys/class/drm/card*/device/hwmon/hwmon*/power1_input")):
+        try:
+            with open(os.path.join(os.path.dirname(path), "name")) as f:
+                if f.read().strip() != "amdgpu":
+                    continue
+            with open(path) as f:
+                int(f.read())
+        except (OSError, ValueError):
+            continue
+
+        def read(path=path):
+            with open(path) as f:
+                return int(f.read()) / 1e6
+        return read, f"sysfs {path}"
+    import shutil
+    import subprocess
+    if shutil.which("amd-smi"):
+        def read_smi():
+            out = subprocess.run(["amd-smi", "metric", "-p", "--json"], capture_output=True, text=True, timeout=10)
+            return float(json.loads(out.stdout)["gpu_data"][0]["power"]["socket_power"]["value"])
+        return read_smi, "amd-smi metric -p (socket_power)"
+    return None, None
+
+
+class PowerSampler:
+    """Samples the socket power every `period` seconds in a thread."""
+
+    def __init__(self, read, period: float = 0.01):
+        import threading
+        self.read, self.period = read, period
+        self.samples: list[tuple[float, float]] = []
+        self._stop = threading.Event()
+        self._th = threading.Thread(target=self._run, daemon=True)
+
+    def _run(self):
+        while not self._stop.is_set():
+            try:
+                self.samples.append((time.perf_counter(), self.read()))
+            except Exception:  # noqa: BLE001  (a missed sample is skipped)
+                pass
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        self._th.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        self._th.join()
+
+    def mean(self, t0: float, t1: float):
+        xs = [w for t, w in self.samples if t0 <= t <= t1]
+        return (sum(xs) / len(xs), len(xs)) if xs else (None, 0)
+
+
+def bench_energy(args) -> dict:
+    """Energy efficiency (Section 4.3's MTEPS/W) of single-source traversals
+    on the bench workload: traversals run back to back for a fixed window
+    while the GPU's socket power is sampled; idle power is sampled before."""
+    import torch
+    import graphgen as gg
+    import paper_1503_04359_amd as dobfs
+    from paper_1503_04359_amd import autotune
+    read, source = power_reader()
+    if read is None:
+        raise RuntimeError("no GPU power reading available (amdgpu hwmon or amd-smi)")
+    t0 = time.time()
+    g = gg.kronecker_device(args.scale, args.edgefactor, seed=args.seed)
+    roots = gg.sample_roots_device(g, args.roots, seed=args.seed + 1_000_000)
+    dg = dobfs.Graph.from_device_pointers(g.offsets_ptr, g.indices_ptr, g.n, g.m, borrow=False, reindex=True)
+    torch.cuda.synchronize()
+    n = g.n
+    g.free()
+    log(f"[energy] kronecker scale {args.scale} resident in {time.time() - t0:.1f}s; power from {source}")
+    tuned = autotune.load_tuned(autotune.tuned_path(args.scale, args.edgefactor))
+    params = dobfs.make_params("edge", **(tuned["params"] if tuned else {}))
+    stream = torch.cuda.current_stream()
+    depth = torch.empty(n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(n, dtype=torch.int32, device="cuda")
+    mc = {}
+    for r in roots:
+        _, _, st = dg.run(int(r), depth, parent, params=params, stats=True, stream=stream)
+        mc[int(r)] = st.m_c
+    torch.cuda.synchronize()
+    with PowerSampler(read) as ps:
+        time.sleep(0.5)
+        i0 = time.perf_counter()
+        time.sleep(args.energy_idle)
+        i1 = time.perf_counter()
+        runs, edges = 0, 0
+        a0 = time.perf_counter()
+        while time.perf_counter() - a0 < args.energy_seconds:
+            for r in roots:
+                dg.run(int(r), depth, parent, params=params, stream=stream)
+                edges += mc[int(r)]
+                runs += 1
+            torch.cuda.synchronize()
+        a1 = time.perf_counter()
+    dg.free()
+    idle_w, n_idle = ps.mean(i0, i1)
+    busy_w, n_busy = ps.mean(a0, a1)
+    secs = a1 - a0
+    teps = edges / secs
+    log(f"[energy] {runs} traversals in {secs:.1f}s: {teps / 1e9:.1f} GTEPS at {busy_w:.0f} W "
+        f"(idle {idle_w:.0f} W; {n_busy} samples): {teps / busy_w / 1e6:.1f} MTEPS/W")
+    return {"metric": f"MTEPS/W (GPU socket power), kronecker scale {args.scale}", "value": round(teps / busy_w / 1e6, 2),
+            "unit": "MTEPS/W", "n_gpus": 1, "steps": runs, "warmup": 1, "ms_per_step": round(secs * 1e3 / runs, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": f"kronecker scale {args.scale} edgefactor {args.edgefactor} seed {args.seed}, "
+                                   f"{args.roots} roots (seed {args.seed + 1_000_000}) run back to back for "
+                                   f"{args.energy_seconds:g} s, degree relabel on, policy edge"
+                                   + (" (tuned parameters)" if tuned else ""),
+                       "power_source": source},
+            "gteps": round(teps / 1e9, 3), "seconds": round(secs, 3), "busy_w": round(busy_w, 1),
+            "idle_w": round(idle_w, 1), "energy_j": round(busy_w * secs, 1), "samples": n_busy,
+            "dynamic_mteps_per_w": round(teps / max(busy_w - idle_w, 1e-9) / 1e6, 2)}
+
+
 def traffic_from_counters(fetch_csv: str, write_csv: str, probe_bytes: int, key: str, out_path: str) -> dict:
     """HBM bytes per launch of each traversal kernel from two rocprofv3
     --pmc runs of the same command (FETCH_SIZE, then WRITE_SIZE, KiB per
@@ -546,7 +671,9 @@ def main() -> int:
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter CSVs of this bench "
                          "(run with --copy-probe) and exit")
-    ap.add_argument("--mode", choices=("single", "batch", "pack", "serve", "chunglu"), default="single")
+    ap.add_argument("--mode", choices=("single", "batch", "pack", "serve", "chunglu", "energy"), default="single")
+    ap.add_argument("--energy-seconds", type=float, default=20.0, help="energy mode: length of the measured window")
+    ap.add_argument("--energy-idle", type=float, default=3.0, help="energy mode: idle power sampled before")
     ap.add_argument("--cl-core", type=int, default=100_000_000, help="chunglu mode: core vertices")
     ap.add_argument("--pack-graphs", type=int, default=2000)
     ap.add_argument("--serve-rates", default="500,2000,8000")
@@ -600,7 +727,8 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     if args.mode != "single":
-        fn = {"batch": bench_batch, "pack": bench_pack, "serve": bench_serve, "chunglu": bench_chunglu}[args.mode]
+        fn = {"batch": bench_batch, "pack": bench_pack, "serve": bench_serve, "chunglu": bench_chunglu,
+              "energy": bench_energy}[args.mode]
         print(json.dumps(fn(args)), flush=True)
         return 0
     stream = torch.cuda.current_stream()

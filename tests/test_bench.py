@@ -7,6 +7,7 @@ import json
 import os
 import shutil
 import subprocess
+import time
 import sys
 
 import pytest
@@ -100,3 +101,17 @@ def test_source_digest_ignores_comments_only(tmp_path, monkeypatch):
 def test_harmonic_mean():
     assert bench.harmonic_mean([1.0, 1.0]) == pytest.approx(1.0)
     assert bench.harmonic_mean([1.0, 3.0]) == pytest.approx(1.5)
+
+
+def test_power_sampler_mean_over_window():
+    vals = iter(range(1, 10_000))
+    with bench.PowerSampler(lambda: float(next(vals)), period=0.001) as ps:
+        time.sleep(0.05)
+        t0 = time.perf_counter()
+        time.sleep(0.05)
+        t1 = time.perf_counter()
+        time.sleep(0.02)
+    mean, n = ps.mean(t0, t1)
+    inside = [w for t, w in ps.samples if t0 <= t <= t1]
+    assert n == len(inside) > 0 and mean == pytest.approx(sum(inside) / len(inside))
+    assert ps.mean(t1 + 10, t1 + 20) == (None, 0)
