@@ -313,6 +313,48 @@ int dobfs_session_counts(dobfs_session_t s, int32_t* active, int32_t* pending, i
 int dobfs_session_levels(dobfs_session_t s, dobfs_level_rec* recs, int32_t cap, int32_t* n);
 int dobfs_session_close(dobfs_session_t s);
 
+/* ---- Hybrid host + GPU traversal: graphs larger than device memory ----
+   The specialized partitioning of Section 3.2 with level-synchronous
+   processing on both processors (Section 3.1, Algorithms 2 and 3) and the
+   direction switching of Section 3.3 taken on both partitions' counts.
+
+   dobfs_hybrid_upload: takes a host CSR (same layout and symmetry
+     requirements as dobfs_graph_upload; host pointers, read during the call
+     only), relabels it by degree class (highest first, ties by caller ID)
+     and splits the internal IDs at h, the smallest multiple of 64 whose
+     GPU share fits gpu_budget_bytes of device memory: rows of [h, n) go to
+     the device with all per-vertex state, rows of [0, h) (the hubs) stay in
+     host memory and are traversed by `threads` host threads.  A budget at
+     or above the whole graph's share puts every row on the GPU (h = 0); a
+     budget that holds the per-vertex state only puts every row on the host.
+     The library owns *out; the stream orders the uploads.
+   dobfs_hybrid_info: *split = host-owned vertices (min(h, n)),
+     *host_entries / *gpu_entries = CSR entries each side holds,
+     *gpu_bytes = device bytes the graph holds.  NULL outputs are skipped.
+   dobfs_hybrid_run: a traversal from `root` (caller ID) on the stream.
+     depth (int32[n]) and parent (int32[n], nullable) are HOST arrays in
+     caller IDs with the meaning of dobfs_run's; the call returns when they
+     are written.  Policies EDGE, PAPER, COST and the forced ones are taken
+     (RANDOM: ENOTSUP); flags and the kernel-shape parameters are ignored.
+     stats (nullable) gets levels, reached, m_c, checked and, when log_cap >
+     0, one record per level with both partitions' counts summed (t_end and
+     kernel_ms are 0).  Runs of one hybrid graph are serialised.
+   dobfs_hybrid_free: releases the graph's device and host memory; NULL is
+     accepted.  The caller ensures no run of the graph is in flight.
+   Errors: EINVAL (NULL pointers, bad CSR, threads outside [1, 1024], a
+     budget below the per-vertex state: 8(n+1) + 8n + 40 ceil(n/64) + 64
+     bytes), ERANGE (root), ENOMEM (device or pinned host allocation),
+     ENOTSUP (policy), EDEVICE. */
+typedef struct dobfs_hybrid_s* dobfs_hybrid_t;
+
+int dobfs_hybrid_upload(const int64_t* offsets, const int32_t* indices, int64_t n, int64_t m,
+                        int64_t gpu_budget_bytes, int32_t threads, void* stream, dobfs_hybrid_t* out);
+int dobfs_hybrid_info(dobfs_hybrid_t h, int64_t* split, int64_t* host_entries, int64_t* gpu_entries,
+                      int64_t* gpu_bytes);
+int dobfs_hybrid_run(dobfs_hybrid_t h, int64_t root, int32_t* depth, int32_t* parent, const dobfs_params* p,
+                     dobfs_stats* stats, void* stream);
+int dobfs_hybrid_free(dobfs_hybrid_t h);
+
 /* Strings for a status; valid forever. */
 const char* dobfs_strerror(int status);
 /* Text of the calling thread's most recent failure ("" if none). */

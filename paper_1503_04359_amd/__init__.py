@@ -54,7 +54,8 @@ POLICIES = {"edge": POLICY_EDGE, "paper": POLICY_PAPER, "td": POLICY_FORCED_TD,
 EXPORTED = ("dobfs_default_params", "dobfs_graph_upload", "dobfs_graph_free", "dobfs_graph_info",
             "dobfs_run", "dobfs_run_noalloc", "dobfs_run_multi", "dobfs_batch_submit", "dobfs_pack_upload", "dobfs_pack_bases",
             "dobfs_pack_run", "dobfs_session_open", "dobfs_session_admit", "dobfs_session_step",
-            "dobfs_session_counts", "dobfs_session_levels", "dobfs_session_close", "dobfs_strerror", "dobfs_last_error")
+            "dobfs_session_counts", "dobfs_session_levels", "dobfs_session_close", "dobfs_hybrid_upload",
+            "dobfs_hybrid_info", "dobfs_hybrid_run", "dobfs_hybrid_free", "dobfs_strerror", "dobfs_last_error")
 
 
 class DobfsError(RuntimeError):
@@ -133,6 +134,14 @@ _lib.dobfs_session_levels.argtypes = [_vp, ctypes.POINTER(LevelRec), ctypes.c_in
 _lib.dobfs_session_close.restype = ctypes.c_int
 _lib.dobfs_session_close.argtypes = [_vp]
 _lib.dobfs_strerror.restype = ctypes.c_char_p
+_lib.dobfs_hybrid_upload.restype = ctypes.c_int
+_lib.dobfs_hybrid_upload.argtypes = [_vp, _vp, _i64, _i64, _i64, ctypes.c_int32, _vp, ctypes.POINTER(_vp)]
+_lib.dobfs_hybrid_info.restype = ctypes.c_int
+_lib.dobfs_hybrid_info.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.dobfs_hybrid_run.restype = ctypes.c_int
+_lib.dobfs_hybrid_run.argtypes = [_vp, _i64, _vp, _vp, ctypes.POINTER(CParams), ctypes.POINTER(CStats), _vp]
+_lib.dobfs_hybrid_free.restype = ctypes.c_int
+_lib.dobfs_hybrid_free.argtypes = [_vp]
 _lib.dobfs_strerror.argtypes = [ctypes.c_int]
 _lib.dobfs_last_error.restype = ctypes.c_char_p
 _lib.dobfs_last_error.argtypes = []
@@ -479,3 +488,68 @@ class Pack(Graph):
                                    ctypes.byref(cs) if cs is not None else None, _stream_ptr(stream)),
                "dobfs_pack_run")
         return depth, parent, _read_stats(cs, log)
+
+
+def hybrid_state_bytes(n: int) -> int:
+    """Device bytes a hybrid graph of n vertices needs before any row: the
+    smallest budget dobfs_hybrid_upload takes."""
+    w = (n + 63) // 64
+    return 8 * (n + 1) + 8 * n + 40 * w + 64
+
+
+class HybridGraph:
+    """A graph split between host memory (the hub rows, traversed by host
+    threads) and the current device (every other row and all per-vertex
+    state), for graphs whose rows do not fit the device budget."""
+
+    def __init__(self, handle: ctypes.c_void_p, n: int, m: int):
+        self._h = handle
+        self.n = n
+        self.m = m
+
+    @classmethod
+    def upload(cls, offsets, indices, *, gpu_budget_bytes: int, threads: int = 8, stream=None) -> "HybridGraph":
+        """offsets int64[n+1], indices int32[m] in host memory (numpy)."""
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        idx = np.ascontiguousarray(indices, dtype=np.int32)
+        n, m = off.shape[0] - 1, idx.shape[0]
+        h = ctypes.c_void_p()
+        _check(_lib.dobfs_hybrid_upload(off.ctypes.data, idx.ctypes.data if m else None, n, m, int(gpu_budget_bytes),
+                                        int(threads), _stream_ptr(stream), ctypes.byref(h)), "dobfs_hybrid_upload")
+        return cls(h, n, m)
+
+    def info(self) -> dict:
+        v = [ctypes.c_int64() for _ in range(4)]
+        _check(_lib.dobfs_hybrid_info(self._h, *[ctypes.byref(x) for x in v]), "dobfs_hybrid_info")
+        return dict(zip(("split", "host_entries", "gpu_entries", "gpu_bytes"), (x.value for x in v)))
+
+    def run(self, root: int, params: CParams | None = None, stats: bool = False, want_parent: bool = True,
+            stream=None):
+        """Returns (depth, parent|None, Stats|None) as host numpy int32 arrays
+        in caller IDs."""
+        depth = np.empty(self.n, dtype=np.int32)
+        parent = np.empty(self.n, dtype=np.int32) if want_parent else None
+        cs, log = _make_stats(stats)
+        _check(_lib.dobfs_hybrid_run(self._h, int(root), depth.ctypes.data,
+                                     parent.ctypes.data if parent is not None else None,
+                                     ctypes.byref(params) if params is not None else None,
+                                     ctypes.byref(cs) if cs is not None else None, _stream_ptr(stream)),
+               "dobfs_hybrid_run")
+        return depth, parent, _read_stats(cs, log)
+
+    def free(self) -> None:
+        if self._h:
+            _check(_lib.dobfs_hybrid_free(self._h), "dobfs_hybrid_free")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()

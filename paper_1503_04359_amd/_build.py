@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdobfs.so")
 STAMP = LIB + ".stamp"
-SOURCES = ["api.hip", "bfs_kernels.hip", "graph_kernels.hip", "reindex.hip", "msbfs.hip"]
+SOURCES = ["api.hip", "bfs_kernels.hip", "graph_kernels.hip", "reindex.hip", "msbfs.hip", "hybrid.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              f"-I{INCLUDE}", f"-I{CSRC}"]

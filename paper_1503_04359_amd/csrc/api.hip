@@ -101,6 +101,9 @@ struct Workspace {
 constexpr int32_t kLogCap = 4096;
 
 }  // namespace
+
+void set_last_error(const char* what, hipError_t e) { (void)fail(DOBFS_OK, what, e); }
+
 }  // namespace dobfs
 
 using namespace dobfs;

@@ -222,6 +222,10 @@ hipError_t launch_aux(const GView& g, const WView& w, const KParams& kp, int gri
 hipError_t launch_finalize(const GView& g, const WView& w, int64_t root, int grid, hipStream_t s);
 hipError_t level_grid(int* grid);
 
+/* Sets the text dobfs_last_error() returns on this thread (api.hip); the
+   HIP error's name is appended when e is not hipSuccess. */
+void set_last_error(const char* what, hipError_t e);
+
 /* Degree relabelling (reindex.hip): builds the internal CSR of a graph whose
    vertices are renumbered by degree, highest first (ties by caller ID),
    every row sorted by internal ID, i.e. highest-degree neighbour first. */
