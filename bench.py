@@ -21,6 +21,13 @@ Other modes (--mode), each printing one JSON line of its own:
          100M core vertices, exponent 2.2, mean degree 20, max 10^6, plus 50
          path tails of 200 vertices (hundreds of levels, several direction
          switches), built on the device; 16 roots, harmonic-mean GTEPS.
+  hybrid Kronecker scale 26 split between host and GPU as for a graph
+         beyond device memory (Section 3.2): the rows of the highest-degree
+         12% of the non-isolated vertices stay in host memory and are
+         traversed by host threads, the rest on the device; 16 roots,
+         harmonic-mean GTEPS of the whole hybrid run (host work, exchanges
+         and the final gather included), with the resident run on the same
+         roots as context.
   energy MTEPS/W: the default workload's traversals back to back for a fixed
          window while the GPU's socket power is sampled (Section 4.3's
          energy case, for the GPU alone).
@@ -616,6 +623,102 @@ def bench_energy(args) -> dict:
             "dynamic_mteps_per_w": round(teps / max(busy_w - idle_w, 1e-9) / 1e6, 2)}
 
 
+def hybrid_budget(deg, host_frac: float) -> tuple[int, int]:
+    """Device budget that leaves the rows of the first ceil(host_frac * n')
+    vertices in the degree-class order (n' = vertices of degree >= 1) to the
+    host; returns (budget bytes, host vertices asked for)."""
+    import numpy as np
+    import paper_1503_04359_amd as dobfs
+    deg = np.asarray(deg, dtype=np.int64)
+    cls = np.zeros_like(deg)
+    nz = deg > 0
+    cls[nz] = np.floor(np.log2(deg[nz])).astype(np.int64) + 1
+    order = np.lexsort((np.arange(deg.shape[0]), -cls))
+    k = int(np.ceil(host_frac * int(nz.sum())))
+    host_entries = int(deg[order[:k]].sum())
+    return dobfs.hybrid_state_bytes(deg.shape[0]) + 4 * (int(deg.sum()) - host_entries), k
+
+
+def bench_hybrid(args) -> dict:
+    """Hybrid host + GPU traversal of a Kronecker graph with the hubs' rows
+    in host memory, against the resident traversal of the same roots."""
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import paper_1503_04359_amd as dobfs
+    scale = args.hybrid_scale
+    t0 = time.time()
+    dgen = gg.kronecker_device(scale, args.edgefactor, seed=args.seed)
+    roots = gg.sample_roots_device(dgen, args.roots, seed=args.seed + 1_000_000)
+    g = dgen.to_host()
+    dgen.free()
+    log(f"[hybrid] kronecker scale {scale} built (n={g.n}, m={g.m}) in {time.time() - t0:.1f}s")
+    budget, k = hybrid_budget(g.degrees(), args.hybrid_host_frac)
+    threads = args.hybrid_threads or min(16, len(os.sched_getaffinity(0)))
+    t0 = time.time()
+    hg = dobfs.HybridGraph.upload(g.offsets, g.indices, gpu_budget_bytes=budget, threads=threads)
+    info = hg.info()
+    log(f"[hybrid] split at {info['split']} ({k} asked): host rows {info['host_entries']} entries, device "
+        f"{info['gpu_entries']} entries, {info['gpu_bytes'] / 2**30:.2f} GiB on the device; upload "
+        f"{time.time() - t0:.1f}s, {threads} host threads")
+    params = dobfs.make_params(args.policy)
+    hdepth = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    hparent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for r in roots[:2]:  # warm-up
+        hg.run(int(r), hdepth, hparent, params=params)
+    teps, times, levels = [], [], []
+    for _ in range(args.steps):
+        for r in roots:
+            t = time.perf_counter()
+            _, _, st = hg.run(int(r), hdepth, hparent, params=params, stats=True)
+            dt = time.perf_counter() - t
+            times.append(dt * 1e3)
+            teps.append(st.m_c / dt)
+            levels.append(st.levels)
+    gteps = harmonic_mean(teps) / 1e9
+    log(f"[hybrid] {gteps:.2f} GTEPS harmonic mean, {np.mean(times):.1f} ms per root")
+    tp = dobfs.make_params(args.policy, flags=dobfs.RUN_TIME_KERNELS)
+    t = time.perf_counter()
+    _, _, st = hg.run(int(roots[0]), hdepth, hparent, params=tp, stats=True)
+    wall = (time.perf_counter() - t) * 1e3
+    prev = 0
+    for rec in st.log:
+        log(f"[hybrid] root {int(roots[0])} level {rec['level']} {'TB'[rec['dir']]}: n_f {rec['n_f']}, "
+            f"checked {rec['checked']}, found {rec['found']}, host {rec['kernel_ms']:.2f} ms, "
+            f"level wall {(rec['t_end'] - prev) / 1e6:.2f} ms")
+        prev = rec["t_end"]
+    log(f"[hybrid] GPU kernels: td {st.td_kernel_ms:.2f} ms, bu {st.bu_kernel_ms:.2f} ms, aux {st.aux_kernel_ms:.2f} ms;"
+        f" levels end at {prev / 1e6:.2f} ms of {wall:.2f} ms")
+    hg.free()
+    del hdepth, hparent
+    # the same roots on the resident path (whole graph on the device)
+    dg = dobfs.Graph.upload(g.offsets, g.indices, reindex=True)
+    stream = torch.cuda.current_stream()
+    depth = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    rt = []
+    for r in roots:
+        dg.run(int(r), depth, params=params, stream=stream)
+    torch.cuda.synchronize()
+    for r in roots:
+        ms, out = _timed(stream, lambda r=r: dg.run(int(r), depth, params=params, stats=True, stream=stream))
+        rt.append(out[2].m_c / (ms * 1e-3))
+    dg.free()
+    res = harmonic_mean(rt) / 1e9
+    log(f"[hybrid] resident run on the same roots: {res:.1f} GTEPS")
+    return {"metric": f"GTEPS (harmonic mean over roots), hybrid host + GPU, kronecker scale {scale}",
+            "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": round(sum(times) / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": f"kronecker scale {scale} edgefactor {args.edgefactor} seed {args.seed}, "
+                                   f"rows of the top {args.hybrid_host_frac:.0%} of non-isolated vertices by degree "
+                                   f"class on the host ({threads} threads), the rest on the device; "
+                                   f"{args.roots} roots (seed {args.seed + 1_000_000}), policy {args.policy}",
+                       "n": g.n, "m": g.m, "split": info["split"], "host_entries": info["host_entries"],
+                       "gpu_entries": info["gpu_entries"], "gpu_bytes": info["gpu_bytes"],
+                       "device_budget": budget, "levels": levels[:len(roots)]},
+            "resident_gteps": round(res, 3), "host": host_spec()}
+
+
 def traffic_from_counters(fetch_csv: str, write_csv: str, probe_bytes: int, key: str, out_path: str) -> dict:
     """HBM bytes per launch of each traversal kernel from two rocprofv3
     --pmc runs of the same command (FETCH_SIZE, then WRITE_SIZE, KiB per
@@ -671,7 +774,12 @@ def main() -> int:
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter CSVs of this bench "
                          "(run with --copy-probe) and exit")
-    ap.add_argument("--mode", choices=("single", "batch", "pack", "serve", "chunglu", "energy"), default="single")
+    ap.add_argument("--mode", choices=("single", "batch", "pack", "serve", "chunglu", "energy", "hybrid"),
+                    default="single")
+    ap.add_argument("--hybrid-scale", type=int, default=26, help="hybrid mode: Kronecker scale")
+    ap.add_argument("--hybrid-host-frac", type=float, default=0.12,
+                    help="hybrid mode: share of the non-isolated vertices (highest degree first) kept on the host")
+    ap.add_argument("--hybrid-threads", type=int, default=0, help="hybrid mode: host threads (0: up to 16)")
     ap.add_argument("--energy-seconds", type=float, default=20.0, help="energy mode: length of the measured window")
     ap.add_argument("--energy-idle", type=float, default=3.0, help="energy mode: idle power sampled before")
     ap.add_argument("--cl-core", type=int, default=100_000_000, help="chunglu mode: core vertices")
@@ -728,7 +836,7 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.mode != "single":
         fn = {"batch": bench_batch, "pack": bench_pack, "serve": bench_serve, "chunglu": bench_chunglu,
-              "energy": bench_energy}[args.mode]
+              "energy": bench_energy, "hybrid": bench_hybrid}[args.mode]
         print(json.dumps(fn(args)), flush=True)
         return 0
     stream = torch.cuda.current_stream()

@@ -81,6 +81,11 @@ typedef struct dobfs_graph_s* dobfs_graph_t; /* opaque, library-owned */
                                       request.  Excludes the two flags below
                                       (EINVAL).                             */
 #define DOBFS_RUN_EAGER 0x4u       /* never use a captured graph             */
+#define DOBFS_RUN_HUB_DECIDES 0x8u /* hybrid runs with the PAPER policy only:
+                                      the host (hub) partition's own next
+                                      frontier decides the top-down ->
+                                      bottom-up switch (Section 3.3); the
+                                      other runs reject it (EINVAL)          */
 
 /* ---- direction policies (Section 3.3) ------------------------------------ */
 #define DOBFS_POLICY_EDGE 0      /* top-down -> bottom-up when the next
@@ -332,18 +337,26 @@ int dobfs_session_close(dobfs_session_t s);
      *host_entries / *gpu_entries = CSR entries each side holds,
      *gpu_bytes = device bytes the graph holds.  NULL outputs are skipped.
    dobfs_hybrid_run: a traversal from `root` (caller ID) on the stream.
-     depth (int32[n]) and parent (int32[n], nullable) are HOST arrays in
+     depth (device int32[n]) and parent (device int32[n], nullable) are in
      caller IDs with the meaning of dobfs_run's; the call returns when they
      are written.  Policies EDGE, PAPER, COST and the forced ones are taken
-     (RANDOM: ENOTSUP); flags and the kernel-shape parameters are ignored.
-     stats (nullable) gets levels, reached, m_c, checked and, when log_cap >
-     0, one record per level with both partitions' counts summed (t_end and
-     kernel_ms are 0).  Runs of one hybrid graph are serialised.
+     (RANDOM: ENOTSUP).  flags: DOBFS_RUN_HUB_DECIDES is taken (PAPER
+     only, else EINVAL); without it the rule sees both partitions' summed
+     counts.  DOBFS_RUN_TIME_KERNELS fills td/bu_kernel_ms with the GPU
+     partition's level kernels and aux_kernel_ms with its mark-apply and
+     parent kernels; the other run flags and the kernel-shape parameters are
+     ignored.  stats (nullable) gets levels, reached, m_c, checked and, when
+     log_cap > 0, one record per level with both partitions' counts summed;
+     in these records t_end is host nanoseconds since the run began, at the
+     level's end (exchanges included), and kernel_ms the host partition's
+     time in the level.  Runs of one hybrid graph are serialised.
+     Host resources held by the graph: the host rows, `threads - 1` worker
+     threads and 24 ceil(n/64) + 12 min(h, n) + 64 bytes of pinned memory.
    dobfs_hybrid_free: releases the graph's device and host memory; NULL is
      accepted.  The caller ensures no run of the graph is in flight.
    Errors: EINVAL (NULL pointers, bad CSR, threads outside [1, 1024], a
-     budget below the per-vertex state: 8(n+1) + 8n + 40 ceil(n/64) + 64
-     bytes), ERANGE (root), ENOMEM (device or pinned host allocation),
+     budget below the per-vertex state: 8(n+1) + 16n + 40 ceil(n/64) +
+     64 bytes), ERANGE (root), ENOMEM (device or pinned host allocation),
      ENOTSUP (policy), EDEVICE. */
 typedef struct dobfs_hybrid_s* dobfs_hybrid_t;
 

@@ -46,7 +46,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ---- status codes and flags (include/dobfs.h) ------------------------------
 OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EBUSY, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 SRC_DEVICE, VALIDATE, VALIDATE_SYMMETRY, REINDEX_DEGREE, BORROW = 0x1, 0x2, 0x4, 0x8, 0x10
-RUN_TIME_KERNELS, RUN_GRAPH, RUN_EAGER = 0x1, 0x2, 0x4
+RUN_TIME_KERNELS, RUN_GRAPH, RUN_EAGER, RUN_HUB_DECIDES = 0x1, 0x2, 0x4, 0x8
 POLICY_EDGE, POLICY_PAPER, POLICY_FORCED_TD, POLICY_FORCED_BU, POLICY_RANDOM, POLICY_COST = 0, 1, 2, 3, 4, 5
 POLICIES = {"edge": POLICY_EDGE, "paper": POLICY_PAPER, "td": POLICY_FORCED_TD,
             "bu": POLICY_FORCED_BU, "random": POLICY_RANDOM, "cost": POLICY_COST}
@@ -494,7 +494,7 @@ def hybrid_state_bytes(n: int) -> int:
     """Device bytes a hybrid graph of n vertices needs before any row: the
     smallest budget dobfs_hybrid_upload takes."""
     w = (n + 63) // 64
-    return 8 * (n + 1) + 8 * n + 40 * w + 64
+    return 8 * (n + 1) + 16 * n + 40 * w + 64
 
 
 class HybridGraph:
@@ -523,15 +523,17 @@ class HybridGraph:
         _check(_lib.dobfs_hybrid_info(self._h, *[ctypes.byref(x) for x in v]), "dobfs_hybrid_info")
         return dict(zip(("split", "host_entries", "gpu_entries", "gpu_bytes"), (x.value for x in v)))
 
-    def run(self, root: int, params: CParams | None = None, stats: bool = False, want_parent: bool = True,
-            stream=None):
-        """Returns (depth, parent|None, Stats|None) as host numpy int32 arrays
-        in caller IDs."""
-        depth = np.empty(self.n, dtype=np.int32)
-        parent = np.empty(self.n, dtype=np.int32) if want_parent else None
+    def run(self, root: int, depth=None, parent=None, params: CParams | None = None, stats: bool = False,
+            want_parent: bool = True, stream=None):
+        """Returns (depth, parent|None, Stats|None): int32 device tensors in
+        caller IDs, written when the call returns."""
+        import torch
+        if depth is None:
+            depth = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        if parent is None and want_parent:
+            parent = torch.empty(self.n, dtype=torch.int32, device="cuda")
         cs, log = _make_stats(stats)
-        _check(_lib.dobfs_hybrid_run(self._h, int(root), depth.ctypes.data,
-                                     parent.ctypes.data if parent is not None else None,
+        _check(_lib.dobfs_hybrid_run(self._h, int(root), _ptr(depth), _ptr(parent) if parent is not None else None,
                                      ctypes.byref(params) if params is not None else None,
                                      ctypes.byref(cs) if cs is not None else None, _stream_ptr(stream)),
                "dobfs_hybrid_run")

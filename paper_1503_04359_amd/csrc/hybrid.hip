@@ -38,7 +38,11 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -63,10 +67,12 @@ struct HybGpu {
   uint64_t* vis;       /* visited bits of [h, n) (the rest unused) */
   const uint64_t* cur; /* frontier of level L, all n vertices */
   uint64_t* nxt;       /* frontier of level L+1, bits of [h, n) */
-  uint64_t* push;      /* top-down: marks for the host partition, bits of [0, h) */
+  uint64_t* push;      /* top-down: marks for the host partition, bits of [0, h),
+                          kept over the levels of a run */
   const uint64_t* pulled; /* top-down: marks from the host partition, bits of [h, n) */
   int32_t* depth;      /* int32[n]: the partition's own entries */
-  int32_t* parent;
+  int32_t* parent;     /* int32[n]: the partition's own entries; entry v < h
+                          holds the GPU vertex whose mark first reached v */
   unsigned long long* cnt; /* found, found_deg, checked, scanned */
 };
 
@@ -85,8 +91,29 @@ __device__ __forceinline__ void hyb_flush(const HybGpu& p, int64_t found, int64_
 }
 
 /* Top-down level on the GPU partition: a wavefront per 64-vertex word of
-   the partition; its frontier vertices are expanded one after another with
-   all lanes striding the row. */
+   the partition.  A frontier vertex with at most kHybLaneRow neighbours is
+   expanded by its own lane; longer rows are taken one after another by the
+   whole wavefront, lanes striding the row. */
+constexpr int64_t kHybLaneRow = 16;
+
+__device__ __forceinline__ void hyb_visit(const HybGpu& p, int32_t L, int32_t u, int32_t v, int64_t& found,
+                                          int64_t& found_deg) {
+  const unsigned long long bit = 1ull << (v & 63);
+  if ((int64_t)v < p.h) {
+    /* owned by the host partition: mark it for the host.  The first mark of
+       v in a run records u, a vertex of depth L, as v's parent should the
+       host first reach v through this mark (at level L) */
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(p.push + (v >> 6));
+    if (!(*w & bit) && !(atomicOr(w, bit) & bit)) p.parent[v] = u;
+  } else if (try_claim(p.vis, v)) {
+    p.depth[v] = L + 1;
+    p.parent[v] = u;
+    atomicOr(reinterpret_cast<unsigned long long*>(p.nxt + (v >> 6)), bit);
+    ++found;
+    found_deg += p.off[v + 1] - p.off[v];
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_hyb_td(HybGpu p, int32_t L) {
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -101,27 +128,19 @@ __global__ void __launch_bounds__(kBlock) k_hyb_td(HybGpu p, int32_t L) {
       b = p.off[u];
       e = p.off[u + 1];
     }
-    uint64_t mm = __ballot(f && e > b);
+    if (e - b <= kHybLaneRow) {
+      for (int64_t k = b; k < e; ++k) hyb_visit(p, L, (int32_t)u, p.idx[k], found, found_deg);
+      checked += e - b;
+    }
+    uint64_t mm = __ballot(e - b > kHybLaneRow);
     while (mm) {
       const int src = __ffsll((unsigned long long)mm) - 1;
       mm &= mm - 1;
       const int32_t uu = (int32_t)__shfl(u, src);
       const int64_t bb = __shfl(b, src), ee = __shfl(e, src);
       for (int64_t k = bb + lane; k < ee; k += kWave) {
-        const int32_t v = p.idx[k];
+        hyb_visit(p, L, uu, p.idx[k], found, found_deg);
         ++checked;
-        const unsigned long long bit = 1ull << (v & 63);
-        if ((int64_t)v < p.h) {
-          /* owned by the host partition: mark it for the host */
-          unsigned long long* w = reinterpret_cast<unsigned long long*>(p.push + (v >> 6));
-          if (!(*w & bit)) atomicOr(w, bit);
-        } else if (try_claim(p.vis, v)) {
-          p.depth[v] = L + 1;
-          p.parent[v] = uu;
-          atomicOr(reinterpret_cast<unsigned long long*>(p.nxt + (v >> 6)), bit);
-          ++found;
-          found_deg += p.off[v + 1] - p.off[v];
-        }
       }
     }
   }
@@ -238,6 +257,23 @@ __global__ void __launch_bounds__(kBlock) k_hyb_init(HybGpu p, int64_t root) {
     }
     if (root >= i * 64 && root < i * 64 + 64) w |= 1ull << (root - i * 64);
     p.vis[i] = w;
+    if (i < p.w0) p.push[i] = 0ull;
+  }
+}
+
+/* Results in caller IDs: entry x takes its internal vertex's depth and the
+   caller ID of its parent. */
+__global__ void __launch_bounds__(kBlock) k_hyb_out(const int32_t* depth_i, const int32_t* parent_i,
+                                                    const int32_t* old2new, const int32_t* new2old, int64_t n,
+                                                    int32_t* depth, int32_t* parent) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += nth) {
+    const int32_t v = old2new[x];
+    depth[x] = depth_i[v];
+    if (parent) {
+      const int32_t pv = parent_i[v];
+      parent[x] = pv >= 0 ? new2old[pv] : -1;
+    }
   }
 }
 
@@ -245,22 +281,79 @@ __global__ void __launch_bounds__(kBlock) k_hyb_init(HybGpu p, int64_t root) {
 
 inline bool get_bit(const uint64_t* bm, int64_t v) { return (bm[v >> 6] >> (v & 63)) & 1ull; }
 
-inline void or_bit(uint64_t* bm, int64_t v) {
-  __atomic_fetch_or(bm + (v >> 6), 1ull << (v & 63), __ATOMIC_RELAXED);
-}
+/* A fixed set of host threads kept for a hybrid graph's lifetime: run(fn)
+   calls fn(t) once for every t in [0, size()), the calling thread taking
+   t = 0, and returns when all calls have returned.  A level hands the pool
+   two or three short jobs, so workers spin on the job counter for up to
+   kSpinUs before blocking on a condition variable, and the caller spins on
+   the count of unfinished workers. */
+class Pool {
+ public:
+  static constexpr int64_t kSpinUs = 200;
 
-/* Runs fn(t) on T threads and joins them. */
-template <class Fn>
-void parallel(int T, Fn fn) {
-  std::vector<std::thread> th;
-  th.reserve((size_t)T);
-  for (int t = 0; t < T; ++t) th.emplace_back(fn, t);
-  for (auto& x : th) x.join();
-}
+  explicit Pool(int n) : n_(n) {
+    for (int t = 1; t < n; ++t) th_.emplace_back([this, t] { loop(t); });
+  }
+  ~Pool() {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      stop_.store(true, std::memory_order_release);
+    }
+    cv_.notify_all();
+    for (auto& x : th_) x.join();
+  }
+  int size() const { return n_; }
+  void run(const std::function<void(int)>& fn) {
+    job_ = &fn;
+    left_.store(n_ - 1, std::memory_order_relaxed);
+    {
+      std::lock_guard<std::mutex> g(mu_);  /* a worker about to block sees the new job */
+      gen_.fetch_add(1, std::memory_order_release);
+    }
+    cv_.notify_all();
+    fn(0);
+    while (left_.load(std::memory_order_acquire) != 0) std::this_thread::yield();
+  }
+
+ private:
+  void loop(int t) {
+    uint64_t seen = 0;
+    for (;;) {
+      uint64_t g = gen_.load(std::memory_order_acquire);
+      const auto t0 = std::chrono::steady_clock::now();
+      for (int i = 0; g == seen && !stop_.load(std::memory_order_acquire); ++i) {
+        if ((i & 255) == 255 &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kSpinUs)) {
+          std::unique_lock<std::mutex> lk(mu_);
+          cv_.wait(lk, [&] {
+            return stop_.load(std::memory_order_acquire) || gen_.load(std::memory_order_acquire) != seen;
+          });
+        }
+        g = gen_.load(std::memory_order_acquire);
+      }
+      if (stop_.load(std::memory_order_acquire)) return;
+      seen = g;
+      (*job_)(t);
+      left_.fetch_sub(1, std::memory_order_acq_rel);
+    }
+  }
+  int n_;
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  const std::function<void(int)>* job_ = nullptr;
+  std::atomic<int> left_{0};
+  std::atomic<uint64_t> gen_{0};
+  std::atomic<bool> stop_{false};
+};
 
 struct Counts {
   int64_t found = 0, found_deg = 0, checked = 0, scanned = 0;
 };
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
 
 }  // namespace
 }  // namespace dobfs
@@ -268,27 +361,46 @@ struct Counts {
 using namespace dobfs;
 
 struct dobfs_hybrid_s {
-  int64_t n = 0, m = 0, h = 0, nn = 0;  /* h: a multiple of 64, possibly past n */
-  int threads = 1;
+  int64_t n = 0, m = 0, h = 0, hv = 0, nn = 0;  /* h: a multiple of 64, possibly past n; hv = min(h, n) */
   int device = 0, grid = 0;
+  std::unique_ptr<Pool> pool;
   /* relabelling (host) */
   std::vector<int32_t> new2old, old2new;
-  /* host partition: rows of [0, min(h, n)), internal IDs */
+  /* host partition: rows of [0, hv), internal IDs, and its per-run state */
   std::vector<int64_t> off_h;
   std::vector<int32_t> idx_h;
-  std::vector<int64_t> deg;     /* degree of every internal vertex */
+  std::vector<int64_t> deg;      /* degree of every internal vertex */
+  std::vector<int32_t> first_h;  /* first neighbour of each host vertex (-1: none), read
+                                    densely by bottom-up levels, where most scans end
+                                    at the first neighbour */
+  std::vector<uint64_t> vis0_h;  /* visited words [0, h/64) at the start of a run */
+  std::vector<uint64_t> vis_h, nxt_h;
+  /* top-down marks of GPU vertices, bucketed by host thread (first index)
+     and by range of 2^bshift bitmap words past h/64 (second index), so that
+     each range is merged into the bitmap by one thread without atomics */
+  std::vector<std::vector<int32_t>> bk;
+  int nb = 1, bshift = 0;
+  /* top-down claims of host vertices as (v << 32 | parent) pairs, bucketed
+     the same way over the words below h/64; the owner of a range claims
+     its vertices, so the claims need no atomics either */
+  std::vector<std::vector<uint64_t>> lk;
+  int nbl = 1, lshift = 0;
   /* GPU partition */
   int64_t* off_g = nullptr;
   int32_t* idx_g = nullptr;
   int64_t gpu_entries = 0;
   uint64_t *vis_g = nullptr, *cur_g = nullptr, *nxt_g = nullptr, *push_g = nullptr, *pulled_g = nullptr;
   int32_t *depth_g = nullptr, *parent_g = nullptr;
+  int32_t *old2new_g = nullptr, *new2old_g = nullptr;
   unsigned long long* cnt_g = nullptr;
-  /* pinned host buffers of the per-level exchange: the whole frontier, the
-     GPU's marks for the host and the host's marks for the GPU (W words
-     each), the GPU's counters of a level and of its apply step */
+  /* pinned host buffers: the whole frontier, the GPU's marks for the host
+     and the host's marks for the GPU (W words each), the GPU's counters of
+     a level and of its apply step; the host partition's depths and parents
+     and the GPU's first-mark parents of host vertices (max(hv, 1) each) */
   uint64_t *cur_x = nullptr, *gmarks_x = nullptr, *hmarks_x = nullptr;
   unsigned long long* cnt_x = nullptr;
+  int32_t *dep_h = nullptr, *par_h = nullptr, *pm_h = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
   std::mutex mu;
 };
 
@@ -312,12 +424,17 @@ uint32_t class_of(int64_t d) {
   return bl;
 }
 
-void free_gpu(dobfs_hybrid_s* H) {
+void release(dobfs_hybrid_s* H) {
   for (void* p : {(void*)H->off_g, (void*)H->idx_g, (void*)H->vis_g, (void*)H->cur_g, (void*)H->nxt_g,
-                  (void*)H->push_g, (void*)H->pulled_g, (void*)H->depth_g, (void*)H->parent_g, (void*)H->cnt_g})
+                  (void*)H->push_g, (void*)H->pulled_g, (void*)H->depth_g, (void*)H->parent_g, (void*)H->cnt_g,
+                  (void*)H->old2new_g, (void*)H->new2old_g})
     if (p) (void)hipFree(p);
-  for (void* p : {(void*)H->cur_x, (void*)H->gmarks_x, (void*)H->hmarks_x, (void*)H->cnt_x})
+  for (void* p : {(void*)H->cur_x, (void*)H->gmarks_x, (void*)H->hmarks_x, (void*)H->cnt_x, (void*)H->dep_h,
+                  (void*)H->par_h, (void*)H->pm_h})
     if (p) (void)hipHostFree(p);
+  for (hipEvent_t e : H->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete H;
 }
 
 HybGpu gpu_view(const dobfs_hybrid_s* H) {
@@ -339,18 +456,24 @@ HybGpu gpu_view(const dobfs_hybrid_s* H) {
   return p;
 }
 
-/* Host partition, one level.  Top-down: frontier vertices of [0, h) are
+/* Host partition, one level.  Top-down: frontier vertices of [0, hv) are
    expanded in tasks of at most kTask row entries (hub rows are long), taken
-   from a shared counter; bottom-up: threads take kBuTake 64-vertex words at
-   a time, each word owned by one thread. */
+   from a shared counter; a neighbour not yet visited goes to the bucket of
+   its word range, and then the owner of each range claims the host
+   vertices and marks the GPU vertices of its range.  Bottom-up: threads
+   take kBuTake 64-vertex words at a time, each word owned by one thread. */
 constexpr int64_t kTask = 1 << 14;
 constexpr int64_t kBuTake = 16;
+constexpr int64_t kRangesPerThread = 8;
 
-Counts host_level(dobfs_hybrid_s* H, int dir, int32_t L, const uint64_t* cur, uint64_t* vis, uint64_t* nxt,
-                  uint64_t* marks, int32_t* depth, int32_t* parent) {
-  const int T = H->threads;
-  const int64_t h = H->h, hv = std::min(H->h, H->n);
-  const int64_t Wh = h / 64;
+Counts host_level(dobfs_hybrid_s* H, int dir, int32_t L, const uint64_t* cur, uint64_t* marks) {
+  Pool& pool = *H->pool;
+  const int T = pool.size();
+  const int64_t h = H->h, hv = H->hv, Wh = h / 64;
+  uint64_t* vis = H->vis_h.data();
+  uint64_t* nxt = H->nxt_h.data();
+  int32_t* depth = H->dep_h;
+  int32_t* parent = H->par_h;
   std::vector<Counts> part((size_t)T);
   if (dir == kDirTD) {
     struct Task {
@@ -366,32 +489,69 @@ Counts host_level(dobfs_hybrid_s* H, int dir, int32_t L, const uint64_t* cur, ui
           tasks.push_back({(int32_t)u, b, std::min(b + kTask, H->off_h[(size_t)u + 1])});
       }
     std::atomic<size_t> next{0};
-    parallel(T, [&](int t) {
+    const int nb = H->nb, bshift = H->bshift, nbl = H->nbl, lshift = H->lshift;
+    pool.run([&](int t) {
       Counts c;
+      std::vector<int32_t>* bk = H->bk.data() + (size_t)t * nb;
+      std::vector<uint64_t>* lk = H->lk.data() + (size_t)t * nbl;
       for (size_t i = next.fetch_add(1); i < tasks.size(); i = next.fetch_add(1)) {
         const Task tk = tasks[i];
+        c.checked += tk.e - tk.b;
         for (int64_t k = tk.b; k < tk.e; ++k) {
           const int32_t v = H->idx_h[(size_t)k];
-          ++c.checked;
-          if ((int64_t)v >= h) {  /* owned by the GPU partition: mark it */
-            if (!get_bit(marks, v)) or_bit(marks, v);
-            continue;
+          if ((int64_t)v >= h) {  /* owned by the GPU partition: to be marked */
+            bk[((v >> 6) - Wh) >> bshift].push_back(v);
+          } else if (!get_bit(vis, v)) {  /* vis does not change in this phase */
+            lk[(v >> 6) >> lshift].push_back(((uint64_t)(uint32_t)v << 32) | (uint32_t)tk.u);
           }
-          const uint64_t bit = 1ull << (v & 63);
-          if (__atomic_load_n(vis + (v >> 6), __ATOMIC_RELAXED) & bit) continue;
-          if (__atomic_fetch_or(vis + (v >> 6), bit, __ATOMIC_RELAXED) & bit) continue;
-          depth[v] = L + 1;
-          parent[v] = tk.u;
-          or_bit(nxt, v);
-          ++c.found;
-          c.found_deg += H->deg[(size_t)v];
         }
       }
       part[(size_t)t] = c;
     });
+    /* owners of the word ranges: each range of either kind is taken by one
+       thread, ranges handed out from a shared counter */
+    const int64_t W = (H->n + 63) / 64;
+    std::vector<Counts> claimed((size_t)T);
+    std::atomic<int> next_range{0};
+    pool.run([&](int t) {
+      Counts c;
+      for (int r = next_range.fetch_add(1); r < nb + nbl; r = next_range.fetch_add(1)) {
+        if (r < nb) {
+          const int64_t w_lo = Wh + ((int64_t)r << bshift), w_hi = std::min(W, Wh + ((int64_t)(r + 1) << bshift));
+          if (w_lo < w_hi) std::memset(marks + w_lo, 0, sizeof(uint64_t) * (size_t)(w_hi - w_lo));
+          for (int src = 0; src < T; ++src) {
+            std::vector<int32_t>& b = H->bk[(size_t)src * nb + r];
+            for (const int32_t v : b) marks[v >> 6] |= 1ull << (v & 63);
+            b.clear();
+          }
+          continue;
+        }
+        for (int src = 0; src < T; ++src) {
+          std::vector<uint64_t>& b = H->lk[(size_t)src * nbl + (r - nb)];
+          for (const uint64_t x : b) {
+            const int32_t v = (int32_t)(x >> 32);
+            const uint64_t bit = 1ull << (v & 63);
+            if (vis[v >> 6] & bit) continue;
+            vis[v >> 6] |= bit;
+            nxt[v >> 6] |= bit;
+            depth[v] = L + 1;
+            parent[v] = (int32_t)(uint32_t)x;
+            ++c.found;
+            c.found_deg += H->deg[(size_t)v];
+          }
+          b.clear();
+        }
+      }
+      claimed[(size_t)t] = c;
+    });
+    for (int t = 0; t < T; ++t) {
+      part[(size_t)t].found += claimed[(size_t)t].found;
+      part[(size_t)t].found_deg += claimed[(size_t)t].found_deg;
+    }
   } else {
+    const int32_t* first = H->first_h.data();
     std::atomic<int64_t> next{0};
-    parallel(T, [&](int t) {
+    pool.run([&](int t) {
       Counts c;
       for (int64_t w0 = next.fetch_add(kBuTake); w0 < Wh; w0 = next.fetch_add(kBuTake)) {
         for (int64_t w = w0; w < std::min(w0 + kBuTake, Wh); ++w) {
@@ -401,18 +561,29 @@ Counts host_level(dobfs_hybrid_s* H, int dir, int32_t L, const uint64_t* cur, ui
             const int j = __builtin_ctzll(x);
             const int64_t v = w * 64 + j;
             const int64_t b = H->off_h[(size_t)v], e = H->off_h[(size_t)v + 1];
-            if (e > b) ++c.scanned;
-            for (int64_t k = b; k < e; ++k) {
-              const int32_t u = H->idx_h[(size_t)k];
-              ++c.checked;
-              if (get_bit(cur, u)) {
-                depth[v] = L + 1;
-                parent[v] = u;
-                fm |= 1ull << j;
-                ++c.found;
-                c.found_deg += e - b;
-                break;
+            if (e == b) continue;
+            ++c.scanned;
+            int32_t par = -1;
+            const int32_t u0 = first[v];
+            ++c.checked;
+            if (get_bit(cur, u0)) {
+              par = u0;
+            } else {
+              for (int64_t k = b + 1; k < e; ++k) {
+                const int32_t u = H->idx_h[(size_t)k];
+                ++c.checked;
+                if (get_bit(cur, u)) {
+                  par = u;
+                  break;
+                }
               }
+            }
+            if (par >= 0) {
+              depth[v] = L + 1;
+              parent[v] = par;
+              fm |= 1ull << j;
+              ++c.found;
+              c.found_deg += e - b;
             }
           }
           nxt[w] = fm;
@@ -432,6 +603,12 @@ Counts host_level(dobfs_hybrid_s* H, int dir, int32_t L, const uint64_t* cur, ui
   return total;
 }
 
+/* [lo, hi) share of thread t of T over [0, n) */
+inline void share(int64_t n, int t, int T, int64_t* lo, int64_t* hi) {
+  *lo = n * t / T;
+  *hi = n * (t + 1) / T;
+}
+
 }  // namespace
 
 extern "C" {
@@ -447,87 +624,123 @@ int dobfs_hybrid_upload(const int64_t* offsets, const int32_t* indices, int64_t 
   if (offsets[0] != 0 || offsets[n] != m) return hfail(DOBFS_EINVAL, "offsets[0] must be 0 and offsets[n] = m");
   for (int64_t v = 0; v < n; ++v)
     if (offsets[v + 1] < offsets[v]) return hfail(DOBFS_EINVAL, "offsets not monotone");
-  for (int64_t k = 0; k < m; ++k)
-    if (indices[k] < 0 || indices[k] >= n) return hfail(DOBFS_EINVAL, "neighbour ID out of range");
+  const int64_t W = (n + 63) / 64;
+  const int64_t fixed = 8 * (n + 1) + 5 * 8 * W + 16 * n + 64;
+  if (gpu_budget_bytes < fixed) return hfail(DOBFS_EINVAL, "device-memory budget below the per-vertex state");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   dobfs_hybrid_s* H = new (std::nothrow) dobfs_hybrid_s();
   if (!H) return hfail(DOBFS_ENOMEM, "hybrid graph");
   H->n = n;
   H->m = m;
-  H->threads = threads;
   auto undo = [&](int st) {
-    free_gpu(H);
-    delete H;
+    release(H);
     return st;
   };
+  try {
+    H->pool.reset(new Pool(threads));
+  } catch (...) {
+    return undo(hfail(DOBFS_ENOMEM, "host threads"));
+  }
+  Pool& pool = *H->pool;
+  {
+    std::atomic<bool> bad{false};
+    pool.run([&](int t) {
+      int64_t lo, hi;
+      share(m, t, pool.size(), &lo, &hi);
+      for (int64_t k = lo; k < hi; ++k)
+        if (indices[k] < 0 || indices[k] >= n) {
+          bad = true;
+          break;
+        }
+    });
+    if (bad) return undo(hfail(DOBFS_EINVAL, "neighbour ID out of range"));
+  }
   hipError_t e;
   if ((e = hipGetDevice(&H->device)) != hipSuccess) return undo(hfail(DOBFS_EDEVICE, "hipGetDevice", e));
   if ((e = level_grid(&H->grid)) != hipSuccess) return undo(hfail(DOBFS_EDEVICE, "occupancy query", e));
 
   /* relabel by degree class, highest first, ties by caller ID (a stable
      counting sort over the classes) */
-  std::vector<uint32_t> cls((size_t)n);
-  uint32_t max_cls = 0;
-  for (int64_t v = 0; v < n; ++v) {
-    cls[(size_t)v] = class_of(offsets[v + 1] - offsets[v]);
-    max_cls = std::max(max_cls, cls[(size_t)v]);
-  }
-  std::vector<int64_t> start((size_t)max_cls + 2, 0);
-  for (int64_t v = 0; v < n; ++v) ++start[(size_t)(max_cls - cls[(size_t)v]) + 1];
-  for (size_t c = 1; c < start.size(); ++c) start[c] += start[c - 1];
-  H->new2old.resize((size_t)n);
-  H->old2new.resize((size_t)n);
-  for (int64_t v = 0; v < n; ++v) {
-    const int64_t pos = start[(size_t)(max_cls - cls[(size_t)v])]++;
-    H->new2old[(size_t)pos] = (int32_t)v;
-    H->old2new[(size_t)v] = (int32_t)pos;
-  }
-  std::vector<int64_t> off_i((size_t)n + 1, 0);
-  H->deg.resize((size_t)n);
-  for (int64_t v = 0; v < n; ++v) {
-    const int32_t o = H->new2old[(size_t)v];
-    H->deg[(size_t)v] = offsets[o + 1] - offsets[o];
-    off_i[(size_t)v + 1] = off_i[(size_t)v] + H->deg[(size_t)v];
-  }
-  H->nn = 0;
-  while (H->nn < n && H->deg[(size_t)H->nn] > 0) ++H->nn;
+  std::vector<int64_t> off_i;
+  std::vector<int32_t> idx_i;
+  try {
+    std::vector<uint32_t> cls((size_t)n);
+    uint32_t max_cls = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      cls[(size_t)v] = class_of(offsets[v + 1] - offsets[v]);
+      max_cls = std::max(max_cls, cls[(size_t)v]);
+    }
+    std::vector<int64_t> start((size_t)max_cls + 2, 0);
+    for (int64_t v = 0; v < n; ++v) ++start[(size_t)(max_cls - cls[(size_t)v]) + 1];
+    for (size_t c = 1; c < start.size(); ++c) start[c] += start[c - 1];
+    H->new2old.resize((size_t)n);
+    H->old2new.resize((size_t)n);
+    for (int64_t v = 0; v < n; ++v) {
+      const int64_t pos = start[(size_t)(max_cls - cls[(size_t)v])]++;
+      H->new2old[(size_t)pos] = (int32_t)v;
+      H->old2new[(size_t)v] = (int32_t)pos;
+    }
+    off_i.assign((size_t)n + 1, 0);
+    H->deg.resize((size_t)n);
+    for (int64_t v = 0; v < n; ++v) {
+      const int32_t o = H->new2old[(size_t)v];
+      H->deg[(size_t)v] = offsets[o + 1] - offsets[o];
+      off_i[(size_t)v + 1] = off_i[(size_t)v] + H->deg[(size_t)v];
+    }
+    H->nn = 0;
+    while (H->nn < n && H->deg[(size_t)H->nn] > 0) ++H->nn;
 
-  /* split: the smallest multiple of 64 whose GPU share fits the budget */
-  const int64_t W = (n + 63) / 64;
-  const int64_t fixed = 8 * (n + 1) + 5 * 8 * W + 8 * n + 64;
-  if (gpu_budget_bytes < fixed) return undo(hfail(DOBFS_EINVAL, "device-memory budget below the per-vertex state"));
-  const int64_t room = (gpu_budget_bytes - fixed) / 4;  /* row entries the GPU can hold */
-  int64_t h = 0;
-  {
+    /* split: the smallest multiple of 64 whose GPU share fits the budget */
+    const int64_t room = (gpu_budget_bytes - fixed) / 4;  /* row entries the GPU can hold */
     int64_t lo = 0, hi = n;  /* first v with m - off_i[v] <= room */
     while (lo < hi) {
       const int64_t mid = (lo + hi) / 2;
       if (m - off_i[(size_t)mid] <= room) hi = mid; else lo = mid + 1;
     }
-    h = (lo + 63) / 64 * 64;  /* may pass n by less than 64: then the host holds every row */
-  }
-  H->h = h;
-  const int64_t hv = std::min(h, n);
+    H->h = (lo + 63) / 64 * 64;  /* may pass n by less than 64: then the host holds every row */
+    H->hv = std::min(H->h, n);
 
-  /* internal rows, sorted by internal ID (highest degree first) */
-  std::vector<int32_t> idx_i((size_t)m);
-  parallel(threads, [&](int t) {
-    const int64_t lo = n * t / threads, hi = n * (t + 1) / threads;
-    for (int64_t v = lo; v < hi; ++v) {
-      const int32_t o = H->new2old[(size_t)v];
-      int32_t* row = idx_i.data() + off_i[(size_t)v];
-      const int64_t d = offsets[o + 1] - offsets[o];
-      for (int64_t k = 0; k < d; ++k) row[k] = H->old2new[(size_t)indices[offsets[o] + k]];
-      std::sort(row, row + d);
-    }
-  });
-  H->off_h.assign(off_i.begin(), off_i.begin() + (hv + 1));
-  H->idx_h.assign(idx_i.begin(), idx_i.begin() + off_i[(size_t)hv]);
+    /* internal rows, sorted by internal ID (highest degree first) */
+    idx_i.resize((size_t)m);
+    std::atomic<int64_t> next{0};
+    pool.run([&](int) {
+      for (int64_t v0 = next.fetch_add(4096); v0 < n; v0 = next.fetch_add(4096))
+        for (int64_t v = v0; v < std::min(v0 + 4096, n); ++v) {
+          const int32_t o = H->new2old[(size_t)v];
+          int32_t* row = idx_i.data() + off_i[(size_t)v];
+          const int64_t d = offsets[o + 1] - offsets[o];
+          for (int64_t k = 0; k < d; ++k) row[k] = H->old2new[(size_t)indices[offsets[o] + k]];
+          std::sort(row, row + d);
+        }
+    });
+    const int64_t h = H->h, hv = H->hv, Wh = h / 64;
+    H->off_h.assign(off_i.begin(), off_i.begin() + (hv + 1));
+    H->idx_h.assign(idx_i.begin(), idx_i.begin() + off_i[(size_t)hv]);
+    H->first_h.assign((size_t)std::max<int64_t>(hv, 1), -1);
+    for (int64_t v = 0; v < hv; ++v)
+      if (off_i[(size_t)v + 1] > off_i[(size_t)v]) H->first_h[(size_t)v] = idx_i[(size_t)off_i[(size_t)v]];
+    H->vis0_h.assign((size_t)std::max<int64_t>(Wh, 1), 0ull);
+    for (int64_t v = 0; v < Wh * 64; ++v)  /* degree-0 vertices and bits past n never take a claim */
+      if (v >= n || H->deg[(size_t)v] == 0) H->vis0_h[(size_t)(v >> 6)] |= 1ull << (v & 63);
+    H->vis_h.assign(H->vis0_h.size(), 0ull);
+    H->nxt_h.assign(H->vis0_h.size(), 0ull);
+    const int64_t Wg = W - Wh;
+    /* at most kRangesPerThread ranges of each kind per thread */
+    const int64_t max_ranges = (int64_t)threads * kRangesPerThread;
+    while (H->bshift < 62 && ((Wg + ((int64_t)1 << H->bshift) - 1) >> H->bshift) > max_ranges) ++H->bshift;
+    H->nb = (int)std::max<int64_t>(1, (Wg + ((int64_t)1 << H->bshift) - 1) >> H->bshift);
+    H->bk.resize((size_t)threads * (size_t)H->nb);
+    while (H->lshift < 62 && ((Wh + ((int64_t)1 << H->lshift) - 1) >> H->lshift) > max_ranges) ++H->lshift;
+    H->nbl = (int)std::max<int64_t>(1, (Wh + ((int64_t)1 << H->lshift) - 1) >> H->lshift);
+    H->lk.resize((size_t)threads * (size_t)H->nbl);
+  } catch (const std::bad_alloc&) {
+    return undo(hfail(DOBFS_ENOMEM, "host partition"));
+  }
+  const int64_t hv = H->hv;
 
   /* GPU partition: every vertex's row slot, the rows of [h, n) filled */
   H->gpu_entries = m - off_i[(size_t)hv];
-  std::vector<int64_t> off_gh((size_t)n + 1, 0);
-  for (int64_t v = hv; v <= n; ++v) off_gh[(size_t)v] = off_i[(size_t)v] - off_i[(size_t)hv];
+  for (int64_t v = 0; v <= n; ++v) off_i[(size_t)v] = v < hv ? 0 : off_i[(size_t)v] - H->off_h[(size_t)hv];
   if ((e = hipMalloc(&H->off_g, sizeof(int64_t) * (size_t)(n + 1))) != hipSuccess ||
       (e = hipMalloc(&H->idx_g, sizeof(int32_t) * (size_t)std::max<int64_t>(H->gpu_entries, 1))) != hipSuccess ||
       (e = hipMalloc(&H->vis_g, sizeof(uint64_t) * (size_t)W)) != hipSuccess ||
@@ -537,18 +750,32 @@ int dobfs_hybrid_upload(const int64_t* offsets, const int32_t* indices, int64_t 
       (e = hipMalloc(&H->pulled_g, sizeof(uint64_t) * (size_t)W)) != hipSuccess ||
       (e = hipMalloc(&H->depth_g, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
       (e = hipMalloc(&H->parent_g, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
-      (e = hipMalloc(&H->cnt_g, sizeof(unsigned long long) * 4)) != hipSuccess)
+      (e = hipMalloc(&H->cnt_g, sizeof(unsigned long long) * 4)) != hipSuccess ||
+      (e = hipMalloc(&H->old2new_g, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
+      (e = hipMalloc(&H->new2old_g, sizeof(int32_t) * (size_t)n)) != hipSuccess)
     return undo(hfail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "GPU partition allocation", e));
   if ((e = hipHostMalloc(&H->cur_x, sizeof(uint64_t) * (size_t)W, hipHostMallocDefault)) != hipSuccess ||
       (e = hipHostMalloc(&H->gmarks_x, sizeof(uint64_t) * (size_t)W, hipHostMallocDefault)) != hipSuccess ||
       (e = hipHostMalloc(&H->hmarks_x, sizeof(uint64_t) * (size_t)W, hipHostMallocDefault)) != hipSuccess ||
-      (e = hipHostMalloc(&H->cnt_x, sizeof(unsigned long long) * 8, hipHostMallocDefault)) != hipSuccess)
+      (e = hipHostMalloc(&H->cnt_x, sizeof(unsigned long long) * 8, hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc(&H->dep_h, sizeof(int32_t) * (size_t)std::max<int64_t>(hv, 1), hipHostMallocDefault)) !=
+          hipSuccess ||
+      (e = hipHostMalloc(&H->par_h, sizeof(int32_t) * (size_t)std::max<int64_t>(hv, 1), hipHostMallocDefault)) !=
+          hipSuccess ||
+      (e = hipHostMalloc(&H->pm_h, sizeof(int32_t) * (size_t)std::max<int64_t>(hv, 1), hipHostMallocDefault)) !=
+          hipSuccess)
     return undo(hfail(DOBFS_ENOMEM, "pinned exchange buffers", e));
-  if ((e = hipMemcpyAsync(H->off_g, off_gh.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, s)) !=
+  if ((e = hipEventCreate(&H->ev[0])) != hipSuccess || (e = hipEventCreate(&H->ev[1])) != hipSuccess)
+    return undo(hfail(DOBFS_EDEVICE, "event creation", e));
+  if ((e = hipMemcpyAsync(H->off_g, off_i.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, s)) !=
           hipSuccess ||
       (H->gpu_entries > 0 &&
-       (e = hipMemcpyAsync(H->idx_g, idx_i.data() + off_i[(size_t)hv], sizeof(int32_t) * (size_t)H->gpu_entries,
+       (e = hipMemcpyAsync(H->idx_g, idx_i.data() + H->off_h[(size_t)hv], sizeof(int32_t) * (size_t)H->gpu_entries,
                            hipMemcpyHostToDevice, s)) != hipSuccess) ||
+      (e = hipMemcpyAsync(H->old2new_g, H->old2new.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(H->new2old_g, H->new2old.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
       (e = hipStreamSynchronize(s)) != hipSuccess)
     return undo(hfail(DOBFS_EDEVICE, "GPU partition upload", e));
   *out = H;
@@ -559,10 +786,10 @@ int dobfs_hybrid_info(dobfs_hybrid_t H, int64_t* split, int64_t* host_entries, i
                       int64_t* gpu_bytes) {
   if (!H) return hfail(DOBFS_EINVAL, "graph is NULL");
   const int64_t W = (H->n + 63) / 64;
-  if (split) *split = std::min(H->h, H->n);
+  if (split) *split = H->hv;
   if (host_entries) *host_entries = (int64_t)H->idx_h.size();
   if (gpu_entries) *gpu_entries = H->gpu_entries;
-  if (gpu_bytes) *gpu_bytes = 8 * (H->n + 1) + 4 * H->gpu_entries + 5 * 8 * W + 8 * H->n + 32;
+  if (gpu_bytes) *gpu_bytes = 8 * (H->n + 1) + 4 * H->gpu_entries + 5 * 8 * W + 16 * H->n + 32;
   return DOBFS_OK;
 }
 
@@ -580,28 +807,40 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
   if (prm.alpha < 1 || prm.beta < 1 || prm.paper_pct < 1 || prm.paper_div < 1 || prm.paper_bu_steps < 1 ||
       prm.kappa_x1000 < 1)
     return hfail(DOBFS_EINVAL, "switching constants must be >= 1");
+  const bool hub_decides = (prm.flags & DOBFS_RUN_HUB_DECIDES) != 0u;
+  if (hub_decides && prm.policy != DOBFS_POLICY_PAPER)
+    return hfail(DOBFS_EINVAL, "DOBFS_RUN_HUB_DECIDES needs the PAPER policy");
+  const bool timed = (prm.flags & DOBFS_RUN_TIME_KERNELS) != 0u;
   if (stats && stats->log_cap > 0 && !stats->log) return hfail(DOBFS_EINVAL, "stats->log is NULL with log_cap > 0");
   std::lock_guard<std::mutex> lk(H->mu);  /* one run of a hybrid graph at a time */
+  const auto t_start = std::chrono::steady_clock::now();
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int64_t n = H->n, h = H->h, hv = std::min(h, n), W = (n + 63) / 64, Wh = h / 64, Wg = W - Wh;
+  Pool& pool = *H->pool;
+  const int T = pool.size();
+  const int64_t n = H->n, h = H->h, hv = H->hv, W = (n + 63) / 64, Wh = h / 64, Wg = W - Wh;
   const int32_t r = H->old2new[(size_t)root];
   uint64_t* cur = H->cur_x;
   uint64_t* gmarks = H->gmarks_x;
   uint64_t* hmarks = H->hmarks_x;
   unsigned long long* cg = H->cnt_x;      /* [0, 4): the level kernel's counters */
   unsigned long long* ca = H->cnt_x + 4;  /* [4, 8): the apply kernel's */
-  /* host state, internal IDs; bits of the GPU's vertices, of degree-0
-     vertices and past n start visited, so the host never claims them */
-  std::vector<uint64_t> vis((size_t)std::max<int64_t>(Wh, 1), 0ull), nxt((size_t)std::max<int64_t>(Wh, 1), 0ull);
-  std::vector<int32_t> dep((size_t)n, -1), par((size_t)n, -1);
-  for (int64_t v = 0; v < Wh * 64; ++v)
-    if (v >= n || H->deg[(size_t)v] == 0) vis[(size_t)(v >> 6)] |= 1ull << (v & 63);
+  double td_ms = 0.0, bu_ms = 0.0, aux_ms = 0.0;
+  auto kernel_ms = [&](double* acc) -> hipError_t {  /* after a synchronize */
+    float ms = 0.f;
+    const hipError_t e = hipEventElapsedTime(&ms, H->ev[0], H->ev[1]);
+    *acc += ms;
+    return e;
+  };
+  /* host state (internal IDs) */
+  std::copy(H->vis0_h.begin(), H->vis0_h.end(), H->vis_h.begin());
+  std::fill(H->dep_h, H->dep_h + std::max<int64_t>(hv, 1), -1);
+  std::fill(H->par_h, H->par_h + std::max<int64_t>(hv, 1), -1);
   std::memset(cur, 0, sizeof(uint64_t) * (size_t)W);
   cur[r >> 6] |= 1ull << (r & 63);
   if (r < hv) {
-    vis[(size_t)(r >> 6)] |= 1ull << (r & 63);
-    dep[(size_t)r] = 0;
-    par[(size_t)r] = r;
+    H->vis_h[(size_t)(r >> 6)] |= 1ull << (r & 63);
+    H->dep_h[(size_t)r] = 0;
+    H->par_h[(size_t)r] = r;
   }
   HybGpu g = gpu_view(H);
   const int grid = H->grid;
@@ -617,42 +856,53 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
   for (int32_t L = 0;; ++L) {
     /* both partitions run level L at once: the GPU's kernel is enqueued,
        then the host threads take the host's share */
-    HYB_HIP(hipMemsetAsync(H->nxt_g, 0, sizeof(uint64_t) * (size_t)W, s), "level reset");
-    HYB_HIP(hipMemsetAsync(H->push_g, 0, sizeof(uint64_t) * (size_t)W, s), "level reset");
+    HYB_HIP(hipMemsetAsync(H->nxt_g + Wh, 0, sizeof(uint64_t) * (size_t)Wg, s), "level reset");
     HYB_HIP(hipMemsetAsync(H->cnt_g, 0, sizeof(unsigned long long) * 4, s), "level reset");
+    if (timed) HYB_HIP(hipEventRecord(H->ev[0], s), "event");
     if (dir == kDirTD) hipLaunchKernelGGL(k_hyb_td, dim3(grid), dim3(kBlock), 0, s, g, L);
     else hipLaunchKernelGGL(k_hyb_bu, dim3(grid), dim3(kBlock), 0, s, g, L);
     HYB_HIP(hipGetLastError(), "level launch");
+    if (timed) HYB_HIP(hipEventRecord(H->ev[1], s), "event");
     HYB_HIP(hipMemcpyAsync(cg, H->cnt_g, sizeof(unsigned long long) * 4, hipMemcpyDeviceToHost, s), "counter copy");
     if (dir == kDirTD && Wh > 0)
       HYB_HIP(hipMemcpyAsync(gmarks, H->push_g, sizeof(uint64_t) * (size_t)Wh, hipMemcpyDeviceToHost, s),
               "marks copy");
-    std::fill(nxt.begin(), nxt.end(), 0ull);
-    if (dir == kDirTD) std::memset(hmarks, 0, sizeof(uint64_t) * (size_t)W);
-    Counts ch = host_level(H, dir, L, cur, vis.data(), nxt.data(), hmarks, dep.data(), par.data());
+    const auto t_host = std::chrono::steady_clock::now();
+    std::fill(H->nxt_h.begin(), H->nxt_h.end(), 0ull);
+    Counts ch;
+    try {
+      ch = host_level(H, dir, L, cur, hmarks);
+    } catch (const std::bad_alloc&) {
+      (void)hipStreamSynchronize(s);
+      return hfail(DOBFS_ENOMEM, "host level");
+    }
+    const double host_ms = ms_since(t_host);
     HYB_HIP(hipStreamSynchronize(s), "level");
+    if (timed) HYB_HIP(kernel_ms(dir == kDirTD ? &td_ms : &bu_ms), "event time");
     ca[0] = ca[1] = ca[2] = ca[3] = 0ull;
     if (dir == kDirTD) {
-      /* the marks each side made for the other (Algorithm 2): the GPU's
-         claim host vertices still unreached, the host's go to the GPU */
+      /* the marks each side made for the other (Algorithm 2): the host's go
+         to the GPU, the GPU's claim host vertices still unreached */
       if (Wg > 0) {
         HYB_HIP(hipMemcpyAsync(H->pulled_g + Wh, hmarks + Wh, sizeof(uint64_t) * (size_t)Wg, hipMemcpyHostToDevice, s),
                 "marks copy");
         HYB_HIP(hipMemsetAsync(H->cnt_g, 0, sizeof(unsigned long long) * 4, s), "apply reset");
+        if (timed) HYB_HIP(hipEventRecord(H->ev[0], s), "event");
         hipLaunchKernelGGL(k_hyb_apply, dim3(grid), dim3(kBlock), 0, s, g, L);
         HYB_HIP(hipGetLastError(), "apply launch");
+        if (timed) HYB_HIP(hipEventRecord(H->ev[1], s), "event");
         HYB_HIP(hipMemcpyAsync(ca, H->cnt_g, sizeof(unsigned long long) * 4, hipMemcpyDeviceToHost, s),
                 "counter copy");
       }
       for (int64_t w = 0; w < Wh; ++w) {
-        const uint64_t nw = gmarks[w] & ~vis[(size_t)w];
+        const uint64_t nw = gmarks[w] & ~H->vis_h[(size_t)w];
         if (!nw) continue;
-        vis[(size_t)w] |= nw;
-        nxt[(size_t)w] |= nw;
+        H->vis_h[(size_t)w] |= nw;
+        H->nxt_h[(size_t)w] |= nw;
         for (uint64_t x = nw; x; x &= x - 1) {
           const int64_t v = w * 64 + __builtin_ctzll(x);
-          dep[(size_t)v] = L + 1;
-          par[(size_t)v] = kPending;
+          H->dep_h[(size_t)v] = L + 1;
+          H->par_h[(size_t)v] = kPending;
           ++ch.found;
           ch.found_deg += H->deg[(size_t)v];
         }
@@ -663,7 +913,8 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
       HYB_HIP(hipMemcpyAsync(cur + Wh, H->nxt_g + Wh, sizeof(uint64_t) * (size_t)Wg, hipMemcpyDeviceToHost, s),
               "frontier copy");
     HYB_HIP(hipStreamSynchronize(s), "frontier copy");
-    std::copy(nxt.begin(), nxt.begin() + Wh, cur);
+    if (timed && dir == kDirTD && Wg > 0) HYB_HIP(kernel_ms(&aux_ms), "event time");
+    std::copy(H->nxt_h.begin(), H->nxt_h.begin() + Wh, cur);
     HYB_HIP(hipMemcpyAsync(H->cur_g, cur, sizeof(uint64_t) * (size_t)W, hipMemcpyHostToDevice, s), "frontier copy");
     const int64_t nfn = ch.found + (int64_t)(cg[0] + ca[0]);
     const int64_t mfn = ch.found_deg + (int64_t)(cg[1] + ca[1]);
@@ -681,6 +932,8 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
       rec.checked = chk;
       rec.found = nfn;
       rec.found_deg = mfn;
+      rec.t_end = (uint64_t)(ms_since(t_start) * 1e6);
+      rec.kernel_ms = (float)host_ms;
     }
     ++log_len;
     reached += nfn;
@@ -692,18 +945,22 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
       levels = L + 1;
       break;
     }
-    int32_t next = dir;  /* the switching rule (Section 3.3) on both partitions' counts */
+    int32_t next = dir;  /* the switching rule (Section 3.3) */
     switch (prm.policy) {
       case DOBFS_POLICY_EDGE:
         if (dir == kDirTD) next = (mfn * (int64_t)prm.alpha > mu_next) ? kDirBU : kDirTD;
         else next = (nfn < n_f && nfn * (int64_t)prm.beta < n) ? kDirTD : kDirBU;
         break;
-      case DOBFS_POLICY_PAPER:
+      case DOBFS_POLICY_PAPER: {
+        /* with the hub partition deciding, its own next frontier (its
+           claims and those the GPU's marks gave it) stands for the whole */
+        const int64_t m_dec = hub_decides ? ch.found_deg : mfn;
         if (dir == kDirTD)
-          next = (bu_phases == 0 && mfn * (int64_t)prm.paper_pct > (n / prm.paper_div) * 100) ? kDirBU : kDirTD;
+          next = (bu_phases == 0 && m_dec * (int64_t)prm.paper_pct > (n / prm.paper_div) * 100) ? kDirBU : kDirTD;
         else
           next = (run >= prm.paper_bu_steps) ? kDirTD : kDirBU;
         break;
+      }
       case DOBFS_POLICY_COST: {
         const int64_t unvisited = H->nn - reached;
         if (dir == kDirTD) next = (mfn * 1000 > (int64_t)prm.kappa_x1000 * unvisited) ? kDirBU : kDirTD;
@@ -720,39 +977,38 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
     m_u = mu_next;
     dir = next;
   }
-  /* deferred parents: each partition finds them in its own rows against
-     both partitions' depths */
-  std::vector<int32_t> dg((size_t)n), pg((size_t)n);
-  HYB_HIP(hipMemcpyAsync(dg.data(), H->depth_g, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s), "depth copy");
-  HYB_HIP(hipStreamSynchronize(s), "depth copy");
-  for (int64_t v = hv; v < n; ++v) dep[(size_t)v] = dg[(size_t)v];
-  if (hv > 0)
-    HYB_HIP(hipMemcpyAsync(H->depth_g, dep.data(), sizeof(int32_t) * (size_t)hv, hipMemcpyHostToDevice, s),
+  /* deferred parents (Section 3.1), collected after the traversal: the
+     GPU partition finds its own in its rows against both partitions'
+     depths; a host vertex first reached through a GPU mark takes the GPU
+     vertex whose mark first reached it, recorded on the device */
+  if (hv > 0) {
+    HYB_HIP(hipMemcpyAsync(H->pm_h, H->parent_g, sizeof(int32_t) * (size_t)hv, hipMemcpyDeviceToHost, s),
+            "parent copy");
+    HYB_HIP(hipMemcpyAsync(H->depth_g, H->dep_h, sizeof(int32_t) * (size_t)hv, hipMemcpyHostToDevice, s),
             "depth copy");
+  }
+  if (timed) HYB_HIP(hipEventRecord(H->ev[0], s), "event");
   hipLaunchKernelGGL(k_hyb_resolve, dim3(grid), dim3(kBlock), 0, s, g, (const int32_t*)H->depth_g);
   HYB_HIP(hipGetLastError(), "resolve launch");
-  HYB_HIP(hipMemcpyAsync(pg.data(), H->parent_g, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s),
-          "parent copy");
-  parallel(H->threads, [&](int t) {
-    const int64_t lo = hv * t / H->threads, hi = hv * (t + 1) / H->threads;
-    for (int64_t v = lo; v < hi; ++v) {
-      if (par[(size_t)v] != kPending) continue;
-      const int32_t want = dep[(size_t)v] - 1;
-      for (int64_t k = H->off_h[(size_t)v]; k < H->off_h[(size_t)v + 1]; ++k)
-        if (dep[(size_t)H->idx_h[(size_t)k]] == want) {
-          par[(size_t)v] = H->idx_h[(size_t)k];
-          break;
-        }
-    }
-  });
+  if (timed) HYB_HIP(hipEventRecord(H->ev[1], s), "event");
   HYB_HIP(hipStreamSynchronize(s), "parent copy");
-  for (int64_t v = hv; v < n; ++v) par[(size_t)v] = pg[(size_t)v];
-  /* caller IDs */
-  for (int64_t v = 0; v < n; ++v) {
-    const int32_t x = H->new2old[(size_t)v];
-    depth[x] = dep[(size_t)v];
-    if (parent) parent[x] = par[(size_t)v] >= 0 ? H->new2old[(size_t)par[(size_t)v]] : -1;
+  if (timed) HYB_HIP(kernel_ms(&aux_ms), "event time");
+  if (hv > 0) {
+    pool.run([&](int t) {
+      int64_t lo, hi;
+      share(hv, t, T, &lo, &hi);
+      for (int64_t v = lo; v < hi; ++v)
+        if (H->par_h[v] == kPending) H->par_h[v] = H->pm_h[v];
+    });
+    HYB_HIP(hipMemcpyAsync(H->parent_g, H->par_h, sizeof(int32_t) * (size_t)hv, hipMemcpyHostToDevice, s),
+            "parent copy");
   }
+  /* caller IDs */
+  hipLaunchKernelGGL(k_hyb_out, dim3(grid), dim3(kBlock), 0, s, (const int32_t*)H->depth_g,
+                     (const int32_t*)H->parent_g, (const int32_t*)H->old2new_g, (const int32_t*)H->new2old_g, n,
+                     depth, parent);
+  HYB_HIP(hipGetLastError(), "output launch");
+  HYB_HIP(hipStreamSynchronize(s), "output");
   if (stats) {
     stats->levels = levels;
     stats->log_len = std::min(log_len, std::max(stats->log_cap, 0));
@@ -761,7 +1017,10 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
     stats->checked = checked_total;
     stats->t_begin = 0;
     stats->level_launches = levels;
-    stats->level_kernel_ms = stats->td_kernel_ms = stats->bu_kernel_ms = stats->aux_kernel_ms = 0.0;
+    stats->level_kernel_ms = td_ms + bu_ms;
+    stats->td_kernel_ms = td_ms;
+    stats->bu_kernel_ms = bu_ms;
+    stats->aux_kernel_ms = aux_ms;
   }
   return DOBFS_OK;
 }
@@ -771,8 +1030,7 @@ int dobfs_hybrid_free(dobfs_hybrid_t H) {
   {
     std::lock_guard<std::mutex> lk(H->mu);
   }
-  free_gpu(H);
-  delete H;
+  release(H);
   return DOBFS_OK;
 }
 

@@ -115,3 +115,20 @@ def test_power_sampler_mean_over_window():
     inside = [w for t, w in ps.samples if t0 <= t <= t1]
     assert n == len(inside) > 0 and mean == pytest.approx(sum(inside) / len(inside))
     assert ps.mean(t1 + 10, t1 + 20) == (None, 0)
+
+
+def test_hybrid_budget_leaves_top_degree_classes_on_the_host():
+    import numpy as np
+    import paper_1503_04359_amd as dobfs
+    rng = np.random.default_rng(5)
+    deg = np.concatenate([rng.integers(1, 9, 500), rng.integers(100, 5000, 20), np.zeros(30, np.int64)])
+    rng.shuffle(deg)
+    budget, k = bench.hybrid_budget(deg, 0.1)
+    nz = int((deg > 0).sum())
+    assert k == int(np.ceil(0.1 * nz))
+    # brute force: order by (bit length of the degree desc, ID asc)
+    order = sorted(range(deg.size), key=lambda v: (-int(deg[v]).bit_length(), v))
+    host = int(sum(deg[v] for v in order[:k]))
+    assert budget == dobfs.hybrid_state_bytes(deg.size) + 4 * (int(deg.sum()) - host)
+    assert bench.hybrid_budget(deg, 0.0)[0] == dobfs.hybrid_state_bytes(deg.size) + 4 * int(deg.sum())
+    assert bench.hybrid_budget(deg, 1.0)[0] == dobfs.hybrid_state_bytes(deg.size)

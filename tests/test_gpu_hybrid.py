@@ -55,6 +55,7 @@ def _parity(dobfs, g, roots, budgets, policies=("edge",), label="", threads=8):
                          f"policy={pol} root={r}")
                     exp, _ = oracle.bfs(g.offsets, g.indices, r)
                     d, p, st = hg.run(r, params=params, stats=True)
+                    d, p = d.cpu().numpy(), p.cpu().numpy()
                     assert np.array_equal(d, exp), (label, budget, pol, r, np.flatnonzero(d != exp)[:10])
                     code, bad = oracle.check_tree(g.offsets, g.indices, r, d, p)
                     assert code == 0, (oracle.CHECK_CODES[code], bad)
@@ -137,9 +138,9 @@ def test_hybrid_repeat_and_errors(dobfs):
     with dobfs.HybridGraph.upload(g.offsets, g.indices, gpu_budget_bytes=_budgets(dobfs, g, (0.5,))[0]) as hg:
         for _ in range(3):
             d, p, _ = hg.run(r)
-            assert np.array_equal(d, exp)
+            assert np.array_equal(d.cpu().numpy(), exp)
         d, p, _ = hg.run(r, want_parent=False)
-        assert p is None and np.array_equal(d, exp)
+        assert p is None and np.array_equal(d.cpu().numpy(), exp)
         with pytest.raises(dobfs.DobfsError) as ei:
             hg.run(g.n)
         assert ei.value.status == dobfs.ERANGE
@@ -157,3 +158,45 @@ def test_hybrid_repeat_and_errors(dobfs):
     with pytest.raises(dobfs.DobfsError) as ei:
         dobfs.HybridGraph.upload(g.offsets, bad, gpu_budget_bytes=1 << 30)
     assert ei.value.status == dobfs.EINVAL
+
+
+def test_hybrid_hub_partition_decides(dobfs):
+    """With DOBFS_RUN_HUB_DECIDES the PAPER rule's top-down -> bottom-up test
+    sees only the host partition's next frontier; the schedule expected from
+    the oracle's depths and the split is recomputed here."""
+    g = gg.kronecker(16, seed=9)
+    roots = gg.sample_roots(g, 4, seed=3)
+    _, _, new2old, old2new = degree_relabel(g)
+    deg = g.degrees().astype(np.int64)
+    budget = _budgets(dobfs, g, (0.4,))[0]
+    with dobfs.HybridGraph.upload(g.offsets, g.indices, gpu_budget_bytes=budget) as hg:
+        split = hg.info()["split"]
+        assert 0 < split < g.n
+        host = old2new < split
+        for pct, div, steps in ((10, 64, 3), (1, 16, 2), (50, 256, 5)):
+            params = dobfs.make_params("paper", paper_pct=pct, paper_div=div, paper_bu_steps=steps,
+                                       flags=dobfs.RUN_HUB_DECIDES)
+            for r in roots:
+                r = int(r)
+                exp, _ = oracle.bfs(g.offsets, g.indices, r)
+                d, p, st = hg.run(r, params=params, stats=True)
+                d, p = d.cpu().numpy(), p.cpu().numpy()
+                assert np.array_equal(d, exp)
+                assert oracle.check_tree(g.offsets, g.indices, r, d, p)[0] == 0
+                want, cur, phases, run = [], 0, 0, 0
+                for L in range(int(exp.max()) + 1):
+                    want.append(cur)
+                    run = run + 1 if cur == 1 else 0
+                    m_host = int(deg[(exp == L + 1) & host].sum())
+                    if cur == 0:
+                        nxt = 1 if (phases == 0 and m_host * pct > (g.n // div) * 100) else 0
+                    else:
+                        nxt = 0 if run >= steps else 1
+                    if cur == 0 and nxt == 1:
+                        phases += 1
+                    cur = nxt
+                assert st.dirs() == want, (pct, div, steps, r, st.dirs(), want)
+    with dobfs.HybridGraph.upload(g.offsets, g.indices, gpu_budget_bytes=budget) as hg:
+        with pytest.raises(dobfs.DobfsError) as ei:
+            hg.run(int(roots[0]), params=dobfs.make_params("edge", flags=dobfs.RUN_HUB_DECIDES))
+        assert ei.value.status == dobfs.EINVAL
