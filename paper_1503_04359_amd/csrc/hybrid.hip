@@ -248,16 +248,18 @@ __global__ void __launch_bounds__(kBlock) k_hyb_init(HybGpu p, int64_t root) {
     p.depth[i] = is_root ? 0 : -1;
     p.parent[i] = is_root ? (int32_t)root : -1;
   }
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < W; i += nth) {
-    /* bits past n, and vertices without a row on the GPU side, start visited */
-    uint64_t w = 0ull;
-    for (int j = 0; j < 64; ++j) {
-      const int64_t v = i * 64 + j;
-      if (v >= p.n || v < p.h || p.off[v + 1] == p.off[v]) w |= 1ull << j;
+  /* a wavefront per visited word: bits past n, vertices without a row on
+     the GPU side and the root start visited */
+  const int lane = lane_id();
+  const int64_t nwaves = nth / kWave;
+  for (int64_t wd = wave_index(); wd < W; wd += nwaves) {
+    const int64_t v = wd * kWave + lane;
+    const bool set = v >= p.n || v < p.h || v == root || p.off[v + 1] == p.off[v];
+    const uint64_t w = __ballot(set);
+    if (lane == 0) {
+      p.vis[wd] = w;
+      if (wd < p.w0) p.push[wd] = 0ull;
     }
-    if (root >= i * 64 && root < i * 64 + 64) w |= 1ull << (root - i * 64);
-    p.vis[i] = w;
-    if (i < p.w0) p.push[i] = 0ull;
   }
 }
 
@@ -349,6 +351,7 @@ class Pool {
 
 struct Counts {
   int64_t found = 0, found_deg = 0, checked = 0, scanned = 0;
+  int64_t marks = 0;  /* host top-down: entries pointing at GPU vertices */
 };
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -370,9 +373,9 @@ struct dobfs_hybrid_s {
   std::vector<int64_t> off_h;
   std::vector<int32_t> idx_h;
   std::vector<int64_t> deg;      /* degree of every internal vertex */
-  std::vector<int32_t> first_h;  /* first neighbour of each host vertex (-1: none), read
-                                    densely by bottom-up levels, where most scans end
-                                    at the first neighbour */
+  std::vector<int32_t> first_h;  /* first neighbour of each vertex of the host's
+                                    words (0: none), read densely by bottom-up
+                                    levels, where most scans end there */
   std::vector<uint64_t> vis0_h;  /* visited words [0, h/64) at the start of a run */
   std::vector<uint64_t> vis_h, nxt_h;
   /* top-down marks of GPU vertices, bucketed by host thread (first index)
@@ -501,6 +504,7 @@ Counts host_level(dobfs_hybrid_s* H, int dir, int32_t L, const uint64_t* cur, ui
           const int32_t v = H->idx_h[(size_t)k];
           if ((int64_t)v >= h) {  /* owned by the GPU partition: to be marked */
             bk[((v >> 6) - Wh) >> bshift].push_back(v);
+            ++c.marks;
           } else if (!get_bit(vis, v)) {  /* vis does not change in this phase */
             lk[(v >> 6) >> lshift].push_back(((uint64_t)(uint32_t)v << 32) | (uint32_t)tk.u);
           }
@@ -513,10 +517,13 @@ Counts host_level(dobfs_hybrid_s* H, int dir, int32_t L, const uint64_t* cur, ui
     const int64_t W = (H->n + 63) / 64;
     std::vector<Counts> claimed((size_t)T);
     std::atomic<int> next_range{0};
+    int64_t n_marks = 0;
+    for (const Counts& c : part) n_marks += c.marks;
     pool.run([&](int t) {
       Counts c;
       for (int r = next_range.fetch_add(1); r < nb + nbl; r = next_range.fetch_add(1)) {
         if (r < nb) {
+          if (n_marks == 0) continue;  /* the marks bitmap is not sent then */
           const int64_t w_lo = Wh + ((int64_t)r << bshift), w_hi = std::min(W, Wh + ((int64_t)(r + 1) << bshift));
           if (w_lo < w_hi) std::memset(marks + w_lo, 0, sizeof(uint64_t) * (size_t)(w_hi - w_lo));
           for (int src = 0; src < T; ++src) {
@@ -556,34 +563,53 @@ Counts host_level(dobfs_hybrid_s* H, int dir, int32_t L, const uint64_t* cur, ui
       for (int64_t w0 = next.fetch_add(kBuTake); w0 < Wh; w0 = next.fetch_add(kBuTake)) {
         for (int64_t w = w0; w < std::min(w0 + kBuTake, Wh); ++w) {
           const uint64_t vw = vis[w];
-          uint64_t fm = 0ull;
-          for (uint64_t x = ~vw; x; x &= x - 1) {
+          const uint64_t unv = ~vw;
+          if (!unv) {
+            nxt[w] = 0ull;
+            continue;
+          }
+          /* every vertex of the word tests its first neighbour, without
+             branches; the rest of a row is read only on a miss */
+          const int32_t* fr = first + w * 64;
+          uint64_t hit = 0ull;
+          for (int j = 0; j < 64; ++j) {
+            const uint32_t u = (uint32_t)fr[j];
+            hit |= ((cur[u >> 6] >> (u & 63)) & 1ull) << j;
+          }
+          hit &= unv;
+          const int n_unv = __builtin_popcountll(unv);
+          c.scanned += n_unv;
+          c.checked += n_unv;
+          for (uint64_t x = hit; x; x &= x - 1) {
+            const int j = __builtin_ctzll(x);
+            const int64_t v = w * 64 + j;
+            depth[v] = L + 1;
+            parent[v] = fr[j];
+            ++c.found;
+            c.found_deg += H->off_h[(size_t)v + 1] - H->off_h[(size_t)v];
+          }
+          uint64_t fm = hit;
+          /* the rows still to read start at scattered places: their first
+             lines are requested together before any is scanned */
+          for (uint64_t x = unv & ~hit; x; x &= x - 1) {
+            const int64_t v = w * 64 + __builtin_ctzll(x);
+            __builtin_prefetch(H->idx_h.data() + H->off_h[(size_t)v] + 1);
+          }
+          for (uint64_t x = unv & ~hit; x; x &= x - 1) {
             const int j = __builtin_ctzll(x);
             const int64_t v = w * 64 + j;
             const int64_t b = H->off_h[(size_t)v], e = H->off_h[(size_t)v + 1];
-            if (e == b) continue;
-            ++c.scanned;
-            int32_t par = -1;
-            const int32_t u0 = first[v];
-            ++c.checked;
-            if (get_bit(cur, u0)) {
-              par = u0;
-            } else {
-              for (int64_t k = b + 1; k < e; ++k) {
-                const int32_t u = H->idx_h[(size_t)k];
-                ++c.checked;
-                if (get_bit(cur, u)) {
-                  par = u;
-                  break;
-                }
+            for (int64_t k = b + 1; k < e; ++k) {
+              const int32_t u = H->idx_h[(size_t)k];
+              ++c.checked;
+              if (get_bit(cur, u)) {
+                depth[v] = L + 1;
+                parent[v] = u;
+                fm |= 1ull << j;
+                ++c.found;
+                c.found_deg += e - b;
+                break;
               }
-            }
-            if (par >= 0) {
-              depth[v] = L + 1;
-              parent[v] = par;
-              fm |= 1ull << j;
-              ++c.found;
-              c.found_deg += e - b;
             }
           }
           nxt[w] = fm;
@@ -599,6 +625,7 @@ Counts host_level(dobfs_hybrid_s* H, int dir, int32_t L, const uint64_t* cur, ui
     total.found_deg += c.found_deg;
     total.checked += c.checked;
     total.scanned += c.scanned;
+    total.marks += c.marks;
   }
   return total;
 }
@@ -716,7 +743,9 @@ int dobfs_hybrid_upload(const int64_t* offsets, const int32_t* indices, int64_t 
     const int64_t h = H->h, hv = H->hv, Wh = h / 64;
     H->off_h.assign(off_i.begin(), off_i.begin() + (hv + 1));
     H->idx_h.assign(idx_i.begin(), idx_i.begin() + off_i[(size_t)hv]);
-    H->first_h.assign((size_t)std::max<int64_t>(hv, 1), -1);
+    /* every vertex of the host's words has an entry; one without a row
+       (never unvisited there) reads vertex 0 */
+    H->first_h.assign((size_t)std::max<int64_t>(Wh * 64, 1), 0);
     for (int64_t v = 0; v < hv; ++v)
       if (off_i[(size_t)v + 1] > off_i[(size_t)v]) H->first_h[(size_t)v] = idx_i[(size_t)off_i[(size_t)v]];
     H->vis0_h.assign((size_t)std::max<int64_t>(Wh, 1), 0ull);
@@ -882,8 +911,10 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
     ca[0] = ca[1] = ca[2] = ca[3] = 0ull;
     if (dir == kDirTD) {
       /* the marks each side made for the other (Algorithm 2): the host's go
-         to the GPU, the GPU's claim host vertices still unreached */
-      if (Wg > 0) {
+         to the GPU (when there are any), the GPU's claim host vertices
+         still unreached */
+      const bool apply = Wg > 0 && ch.marks > 0;
+      if (apply) {
         HYB_HIP(hipMemcpyAsync(H->pulled_g + Wh, hmarks + Wh, sizeof(uint64_t) * (size_t)Wg, hipMemcpyHostToDevice, s),
                 "marks copy");
         HYB_HIP(hipMemsetAsync(H->cnt_g, 0, sizeof(unsigned long long) * 4, s), "apply reset");
@@ -907,15 +938,11 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
           ch.found_deg += H->deg[(size_t)v];
         }
       }
+      if (apply) {
+        HYB_HIP(hipStreamSynchronize(s), "apply");
+        if (timed) HYB_HIP(kernel_ms(&aux_ms), "event time");
+      }
     }
-    /* the next frontier's two parts, so that both sides hold all of it */
-    if (Wg > 0)
-      HYB_HIP(hipMemcpyAsync(cur + Wh, H->nxt_g + Wh, sizeof(uint64_t) * (size_t)Wg, hipMemcpyDeviceToHost, s),
-              "frontier copy");
-    HYB_HIP(hipStreamSynchronize(s), "frontier copy");
-    if (timed && dir == kDirTD && Wg > 0) HYB_HIP(kernel_ms(&aux_ms), "event time");
-    std::copy(H->nxt_h.begin(), H->nxt_h.begin() + Wh, cur);
-    HYB_HIP(hipMemcpyAsync(H->cur_g, cur, sizeof(uint64_t) * (size_t)W, hipMemcpyHostToDevice, s), "frontier copy");
     const int64_t nfn = ch.found + (int64_t)(cg[0] + ca[0]);
     const int64_t mfn = ch.found_deg + (int64_t)(cg[1] + ca[1]);
     const int64_t chk = ch.checked + (int64_t)cg[2];
@@ -976,6 +1003,21 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
     m_f = mfn;
     m_u = mu_next;
     dir = next;
+    /* the next frontier: the host's part goes to the device, whose own part
+       is already in place (the two device bitmaps swap roles); the device's
+       part comes to the host only for a bottom-up level, the one kind of
+       host level that reads it */
+    std::copy(H->nxt_h.begin(), H->nxt_h.begin() + Wh, cur);
+    if (Wh > 0)
+      HYB_HIP(hipMemcpyAsync(H->nxt_g, cur, sizeof(uint64_t) * (size_t)Wh, hipMemcpyHostToDevice, s),
+              "frontier copy");
+    if (dir == kDirBU && Wg > 0)
+      HYB_HIP(hipMemcpyAsync(cur + Wh, H->nxt_g + Wh, sizeof(uint64_t) * (size_t)Wg, hipMemcpyDeviceToHost, s),
+              "frontier copy");
+    HYB_HIP(hipStreamSynchronize(s), "frontier copy");
+    std::swap(H->cur_g, H->nxt_g);
+    g = gpu_view(H);
+    if (stats && log_len - 1 < stats->log_cap) stats->log[log_len - 1].t_end = (uint64_t)(ms_since(t_start) * 1e6);
   }
   /* deferred parents (Section 3.1), collected after the traversal: the
      GPU partition finds its own in its rows against both partitions'
