@@ -661,7 +661,8 @@ def bench_hybrid(args) -> dict:
     log(f"[hybrid] split at {info['split']} ({k} asked): host rows {info['host_entries']} entries, device "
         f"{info['gpu_entries']} entries, {info['gpu_bytes'] / 2**30:.2f} GiB on the device; upload "
         f"{time.time() - t0:.1f}s, {threads} host threads")
-    params = dobfs.make_params(args.policy, alpha=args.hybrid_alpha)
+    flags = dobfs.RUN_HUB_DECIDES if args.hybrid_hub_decides else 0
+    params = dobfs.make_params(args.policy, alpha=args.hybrid_alpha, flags=flags)
     hdepth = torch.empty(g.n, dtype=torch.int32, device="cuda")
     hparent = torch.empty(g.n, dtype=torch.int32, device="cuda")
     for r in roots[:2]:  # warm-up
@@ -677,7 +678,7 @@ def bench_hybrid(args) -> dict:
             levels.append(st.levels)
     gteps = harmonic_mean(teps) / 1e9
     log(f"[hybrid] {gteps:.2f} GTEPS harmonic mean, {np.mean(times):.1f} ms per root")
-    tp = dobfs.make_params(args.policy, alpha=args.hybrid_alpha, flags=dobfs.RUN_TIME_KERNELS)
+    tp = dobfs.make_params(args.policy, alpha=args.hybrid_alpha, flags=flags | dobfs.RUN_TIME_KERNELS)
     t = time.perf_counter()
     _, _, st = hg.run(int(roots[0]), hdepth, hparent, params=tp, stats=True)
     wall = (time.perf_counter() - t) * 1e3
@@ -715,7 +716,8 @@ def bench_hybrid(args) -> dict:
                                    f"rows of the top {args.hybrid_host_frac:.0%} of non-isolated vertices by degree "
                                    f"class on the host ({threads} threads), the rest on the device; "
                                    f"{args.roots} roots (seed {args.seed + 1_000_000}), policy {args.policy} "
-                                   f"with alpha {args.hybrid_alpha}",
+                                   + (f"with alpha {args.hybrid_alpha}" if args.policy == "edge" else "")
+                                   + (", the host partition deciding the switch" if args.hybrid_hub_decides else ""),
                        "n": g.n, "m": g.m, "split": info["split"], "host_entries": info["host_entries"],
                        "gpu_entries": info["gpu_entries"], "gpu_bytes": info["gpu_bytes"],
                        "device_budget": budget, "levels": levels[:len(roots)]},
@@ -783,6 +785,8 @@ def main() -> int:
     ap.add_argument("--hybrid-host-frac", type=float, default=0.12,
                     help="hybrid mode: share of the non-isolated vertices (highest degree first) kept on the host")
     ap.add_argument("--hybrid-threads", type=int, default=0, help="hybrid mode: host threads (0: up to 16)")
+    ap.add_argument("--hybrid-hub-decides", action="store_true",
+                    help="hybrid mode: the host partition's own next frontier decides the switch (PAPER policy)")
     ap.add_argument("--hybrid-alpha", type=int, default=56,
                     help="hybrid mode: EDGE policy's alpha (a sweep at scale 26 put the hybrid's best at 56-112; the "
                          "resident path's 14 leaves hub rows to host top-down levels)")
