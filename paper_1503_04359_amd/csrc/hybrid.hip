@@ -288,7 +288,9 @@ inline bool get_bit(const uint64_t* bm, int64_t v) { return (bm[v >> 6] >> (v & 
    t = 0, and returns when all calls have returned.  A level hands the pool
    two or three short jobs, so workers spin on the job counter for up to
    kSpinUs before blocking on a condition variable, and the caller spins on
-   the count of unfinished workers. */
+   the count of unfinished workers.  An exception thrown by fn in any thread
+   is caught there and reported to the caller of run() as std::bad_alloc,
+   the one kind the jobs can throw, once every call has returned. */
 class Pool {
  public:
   static constexpr int64_t kSpinUs = 200;
@@ -307,14 +309,20 @@ class Pool {
   int size() const { return n_; }
   void run(const std::function<void(int)>& fn) {
     job_ = &fn;
+    failed_.store(false, std::memory_order_relaxed);
     left_.store(n_ - 1, std::memory_order_relaxed);
     {
       std::lock_guard<std::mutex> g(mu_);  /* a worker about to block sees the new job */
       gen_.fetch_add(1, std::memory_order_release);
     }
     cv_.notify_all();
-    fn(0);
+    try {
+      fn(0);
+    } catch (...) {
+      failed_.store(true, std::memory_order_relaxed);
+    }
     while (left_.load(std::memory_order_acquire) != 0) std::this_thread::yield();
+    if (failed_.load(std::memory_order_relaxed)) throw std::bad_alloc();
   }
 
  private:
@@ -335,7 +343,11 @@ class Pool {
       }
       if (stop_.load(std::memory_order_acquire)) return;
       seen = g;
-      (*job_)(t);
+      try {
+        (*job_)(t);
+      } catch (...) {
+        failed_.store(true, std::memory_order_relaxed);
+      }
       left_.fetch_sub(1, std::memory_order_acq_rel);
     }
   }
@@ -347,6 +359,7 @@ class Pool {
   std::atomic<int> left_{0};
   std::atomic<uint64_t> gen_{0};
   std::atomic<bool> stop_{false};
+  std::atomic<bool> failed_{false};
 };
 
 struct Counts {
@@ -860,7 +873,10 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
     *acc += ms;
     return e;
   };
-  /* host state (internal IDs) */
+  /* host state (internal IDs); buckets left filled by a failed run are
+     emptied */
+  for (auto& b : H->bk) b.clear();
+  for (auto& b : H->lk) b.clear();
   std::copy(H->vis0_h.begin(), H->vis0_h.end(), H->vis_h.begin());
   std::fill(H->dep_h, H->dep_h + std::max<int64_t>(hv, 1), -1);
   std::fill(H->par_h, H->par_h + std::max<int64_t>(hv, 1), -1);
