@@ -452,7 +452,8 @@ def bench_serve(args) -> dict:
     ex = serve.GpuExecutor(graphs, params=params)
     free, _ = torch.cuda.mem_get_info()
     budget = max(0, free - (16 << 30))
-    srv = serve.Server(ex, memory_budget=budget)
+    srv = serve.Server(ex, memory_budget=budget, plain_max=args.serve_plain_max,
+                       plain_concurrency=args.serve_plain_concurrency)
     # warm-up: one session and one plain run per graph
     warm = [serve.Query(i, gid, int(pools[gid][0]), 0.0) for i, gid in enumerate(range(len(graphs)))]
     srv.serve(warm, mode="batched", drain_s=30.0)
@@ -466,7 +467,10 @@ def bench_serve(args) -> dict:
         for mode in ("batched", "plain"):
             tr = [serve.Query(q.qid, q.gid, q.root, q.t_arrival) for q in trace]
             torch.cuda.synchronize()
+            solo0 = srv.solo_runs
             rep, _ = srv.serve(tr, mode=mode, drain_s=args.serve_drain)
+            if mode == "batched":
+                row["plain_runs_in_batched"] = srv.solo_runs - solo0
             all_q.extend(q for q in tr if q.t_done is not None)
             row[mode] = rep.as_dict()
             row[mode]["_queries"] = tr
@@ -496,7 +500,9 @@ def bench_serve(args) -> dict:
                                    f"{args.edgefactor}, seeds 5000+j), Poisson arrivals (seed 6000+rate) for "
                                    f"{args.serve_duration:g} s per rate, uniform graph choice, roots from 256 per "
                                    f"graph (seed 5000+j+10^6), degree relabel {args.reindex}, chunk "
-                                   f"{args.serve_chunk} levels, drain {args.serve_drain:g} s",
+                                   f"{args.serve_chunk} levels, drain {args.serve_drain:g} s, plain runs while at "
+                                   f"most {args.serve_plain_max} queries wait on an idle graph, at most "
+                                   f"{args.serve_plain_concurrency} such runs at once",
                        "rates": rates},
             "rates": results}
 
@@ -798,6 +804,10 @@ def main() -> int:
     ap.add_argument("--serve-duration", type=float, default=10.0)
     ap.add_argument("--serve-drain", type=float, default=5.0)
     ap.add_argument("--serve-chunk", type=int, default=4)
+    ap.add_argument("--serve-plain-max", type=int, default=8,
+                    help="serve mode: waiting queries of an idle graph run plain up to this many")
+    ap.add_argument("--serve-plain-concurrency", type=int, default=2,
+                    help="serve mode: plain runs of the batched mode that may execute at once")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--param", action="append", default=[], metavar="NAME=VALUE",
                     help="override a dobfs_params field (e.g. alpha=14), repeatable")

@@ -6,10 +6,15 @@ Two ways to serve the same open-loop trace of timed arrivals:
   the 64-slot batched traversal running; arrived queries join between level
   chunks as slots and device memory allow, and leave as soon as their own
   traversal ends, so queries that arrive while others run share the device
-  with them.  A query that finds its graph idle and nobody waiting behind
-  it runs as a plain single-source traversal instead (``solo_plain``): a
-  session level sweeps the whole graph, which only pays off when several
-  queries share it.
+  with them.  While no session traversal of the graph is in flight and at
+  most ``plain_max`` queries wait for it, the oldest runs as a plain
+  single-source traversal instead (``solo_plain``): a session level sweeps
+  the whole graph, which only pays off when many queries share it (a
+  64-root batch costs about as much as 15 plain runs), so a few waiting
+  queries finish sooner one after another.  At most ``plain_concurrency``
+  such plain runs execute at once over all graphs, started in arrival order
+  (the oldest waiting query first, whatever its graph), so that at low load
+  the batched mode serves like the plain one.
 * ``plain``: one worker serves the queries one at a time in arrival order,
   each a single-source traversal of its own.
 
@@ -20,6 +25,7 @@ device, so it can be driven by a CPU stand-in.
 """
 from __future__ import annotations
 
+import heapq
 import math
 import threading
 import time
@@ -135,17 +141,49 @@ class Server:
     """Serves a trace through an executor; see the module text."""
 
     def __init__(self, executor: Executor, memory_budget: int, slots: int = 64,
-                 clock: Callable[[], float] = time.perf_counter, poll_s: float = 2e-4, solo_plain: bool = True):
+                 clock: Callable[[], float] = time.perf_counter, poll_s: float = 2e-4, solo_plain: bool = True,
+                 plain_max: int = 1, plain_concurrency: int = 1):
+        if plain_max < 0:
+            raise ValueError("plain_max must be >= 0")
+        if plain_concurrency < 1:
+            raise ValueError("plain_concurrency must be >= 1")
         self.ex = executor
         self.budget = MemoryBudget(memory_budget)
         self.slots = slots
         self.clock = clock
         self.poll_s = poll_s
         self.solo_plain = solo_plain
+        self.plain_max = plain_max if solo_plain else 0
+        self._plain_cv = threading.Condition()
+        self._plain_q: list = []  # (arrival, qid) of the queries waiting to run plain
+        self._plain_busy = 0
+        self._plain_conc = plain_concurrency
         self.solo_runs = 0
         self._count_lock = threading.Lock()
 
     # ---- batched -----------------------------------------------------------
+    def _plain_acquire(self, key, t0: float, deadline: float) -> bool:
+        """Waits until query `key` = (arrival, qid) is the oldest waiting for
+        a plain run and a run may start; False if the deadline passes."""
+        with self._plain_cv:
+            heapq.heappush(self._plain_q, key)
+            while not (self._plain_busy < self._plain_conc and self._plain_q[0] == key):
+                if self.clock() - t0 > deadline:
+                    self._plain_q.remove(key)
+                    heapq.heapify(self._plain_q)
+                    self._plain_cv.notify_all()
+                    return False
+                self._plain_cv.wait(timeout=0.01)
+            heapq.heappop(self._plain_q)
+            self._plain_busy += 1
+            self._plain_cv.notify_all()
+            return True
+
+    def _plain_release(self) -> None:
+        with self._plain_cv:
+            self._plain_busy -= 1
+            self._plain_cv.notify_all()
+
     def _graph_worker(self, gid: int, queries: list[Query], t0: float, deadline: float,
                       results: Optional[dict]) -> None:
         ex = self.ex
@@ -158,10 +196,18 @@ class Server:
                 now = self.clock() - t0
                 if now > deadline:
                     break
-                if (self.solo_plain and not inflight and nxt < len(queries) and queries[nxt].t_arrival <= now
-                        and (nxt + 1 >= len(queries) or queries[nxt + 1].t_arrival > now)
-                        and self.budget.take(need)):
+                waiting = 0
+                while (waiting <= self.plain_max and nxt + waiting < len(queries)
+                       and queries[nxt + waiting].t_arrival <= now):
+                    waiting += 1
+                if not inflight and 1 <= waiting <= self.plain_max:
                     q = queries[nxt]
+                    if not self._plain_acquire((q.t_arrival, q.qid), t0, deadline):
+                        break
+                    if not self.budget.take(need):
+                        self._plain_release()
+                        time.sleep(self.poll_s)
+                        continue
                     nxt += 1
                     try:
                         res = ex.run_plain(gid, q.root)
@@ -169,6 +215,8 @@ class Server:
                         q.error = f"{type(e).__name__}: {e}"
                         self.budget.give(need)
                         continue
+                    finally:
+                        self._plain_release()
                     q.t_done = self.clock() - t0
                     with self._count_lock:
                         self.solo_runs += 1

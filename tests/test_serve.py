@@ -124,3 +124,64 @@ def test_drain_limit_leaves_queries_unfinished():
     rep, _ = srv.serve(trace, mode="plain", drain_s=0.2)
     assert rep.unfinished > 0 and rep.completed > 0
     assert rep.p99_ms is None  # the 99th percentile lies among the unfinished
+
+
+@pytest.mark.parametrize("plain_max,expect_plain", [(1, 0), (3, 3), (8, 3), (0, 0)])
+def test_plain_runs_below_the_session_threshold(plain_max, expect_plain):
+    """Three queries arrive together on an idle graph: with plain_max >= 3
+    they all run plain, one after another; below that they share a session.
+    A lone later arrival runs plain whenever plain_max >= 1."""
+    gs = _graphs()
+    ex = CpuExecutor([(g.offsets, g.indices) for g in gs])
+    trace = [serve.Query(0, 0, 3, 0.0), serve.Query(1, 0, 7, 0.0), serve.Query(2, 0, 11, 0.0),
+             serve.Query(3, 0, 5, 0.2)]
+    srv = serve.Server(ex, memory_budget=1 << 30, plain_max=plain_max)
+    rep, res = srv.serve(trace, mode="batched", drain_s=30.0, keep_results=True)
+    assert rep.completed == len(trace)
+    exp = _expected(gs, trace)
+    for q in trace:
+        assert np.array_equal(res[q.qid], exp[(q.gid, q.root)])
+    assert srv.solo_runs == expect_plain + (1 if plain_max >= 1 else 0)
+
+
+def test_plain_max_must_not_be_negative():
+    with pytest.raises(ValueError):
+        serve.Server(CpuExecutor([]), memory_budget=1, plain_max=-1)
+    with pytest.raises(ValueError):
+        serve.Server(CpuExecutor([]), memory_budget=1, plain_concurrency=0)
+
+
+def test_plain_runs_never_overlap_across_graphs():
+    """With plain_concurrency 1 the graph workers' plain runs execute one
+    at a time; results still equal the oracle's."""
+    import threading
+
+    class Counting(CpuExecutor):
+        def __init__(self, graphs):
+            super().__init__(graphs)
+            self.lock = threading.Lock()
+            self.now = 0
+            self.peak = 0
+
+        def run_plain(self, gid, root):
+            import time
+            with self.lock:
+                self.now += 1
+                self.peak = max(self.peak, self.now)
+            time.sleep(0.002)
+            try:
+                return super().run_plain(gid, root)
+            finally:
+                with self.lock:
+                    self.now -= 1
+
+    gs = _graphs()
+    ex = Counting([(g.offsets, g.indices) for g in gs])
+    trace = serve.poisson_trace(300.0, 0.3, len(gs), _roots(gs), seed=7)
+    srv = serve.Server(ex, memory_budget=1 << 30, plain_max=8, plain_concurrency=1)
+    rep, res = srv.serve(trace, mode="batched", drain_s=30.0, keep_results=True)
+    assert rep.completed == len(trace) and srv.solo_runs > 0
+    assert ex.peak == 1
+    exp = _expected(gs, trace)
+    for q in trace:
+        assert np.array_equal(res[q.qid], exp[(q.gid, q.root)])
