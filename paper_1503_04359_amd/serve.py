@@ -142,7 +142,7 @@ class Server:
 
     def __init__(self, executor: Executor, memory_budget: int, slots: int = 64,
                  clock: Callable[[], float] = time.perf_counter, poll_s: float = 2e-4, solo_plain: bool = True,
-                 plain_max: int = 1, plain_concurrency: int = 1):
+                 plain_max: int = 8, plain_concurrency: int = 2):
         if plain_max < 0:
             raise ValueError("plain_max must be >= 0")
         if plain_concurrency < 1:

@@ -85,7 +85,8 @@ def test_failure_injection_fails_only_the_session_queries():
     gs = _graphs()
     ex = CpuExecutor([(g.offsets, g.indices) for g in gs], fail_steps=(5,))
     trace = serve.poisson_trace(500.0, 0.3, len(gs), _roots(gs), seed=3)
-    srv = serve.Server(ex, memory_budget=1 << 30)
+    # plain runs only for a lone query, so that sessions carry most queries
+    srv = serve.Server(ex, memory_budget=1 << 30, plain_max=1)
     rep, res = srv.serve(trace, mode="batched", drain_s=30.0, keep_results=True)
     assert rep.failed >= 1
     assert rep.completed + rep.failed == len(trace)
