@@ -873,24 +873,30 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
     *acc += ms;
     return e;
   };
-  /* host state (internal IDs); buckets left filled by a failed run are
-     emptied */
+  /* the device's state is set up while the host threads reset the host's
+     (internal IDs); buckets left filled by a failed run are emptied */
+  HybGpu g = gpu_view(H);
+  const int grid = H->grid;
+  hipLaunchKernelGGL(k_hyb_init, dim3(grid), dim3(kBlock), 0, s, g, (int64_t)r);
+  HYB_HIP(hipGetLastError(), "init launch");
   for (auto& b : H->bk) b.clear();
   for (auto& b : H->lk) b.clear();
-  std::copy(H->vis0_h.begin(), H->vis0_h.end(), H->vis_h.begin());
-  std::fill(H->dep_h, H->dep_h + std::max<int64_t>(hv, 1), -1);
-  std::fill(H->par_h, H->par_h + std::max<int64_t>(hv, 1), -1);
-  std::memset(cur, 0, sizeof(uint64_t) * (size_t)W);
+  pool.run([&](int t) {
+    int64_t lo, hi;
+    share((int64_t)H->vis0_h.size(), t, T, &lo, &hi);
+    std::copy(H->vis0_h.begin() + lo, H->vis0_h.begin() + hi, H->vis_h.begin() + lo);
+    share(std::max<int64_t>(hv, 1), t, T, &lo, &hi);
+    std::fill(H->dep_h + lo, H->dep_h + hi, -1);
+    std::fill(H->par_h + lo, H->par_h + hi, -1);
+    share(W, t, T, &lo, &hi);
+    std::memset(cur + lo, 0, sizeof(uint64_t) * (size_t)(hi - lo));
+  });
   cur[r >> 6] |= 1ull << (r & 63);
   if (r < hv) {
     H->vis_h[(size_t)(r >> 6)] |= 1ull << (r & 63);
     H->dep_h[(size_t)r] = 0;
     H->par_h[(size_t)r] = r;
   }
-  HybGpu g = gpu_view(H);
-  const int grid = H->grid;
-  hipLaunchKernelGGL(k_hyb_init, dim3(grid), dim3(kBlock), 0, s, g, (int64_t)r);
-  HYB_HIP(hipGetLastError(), "init launch");
   HYB_HIP(hipMemcpyAsync(H->cur_g, cur, sizeof(uint64_t) * (size_t)W, hipMemcpyHostToDevice, s), "frontier copy");
 
   int32_t dir = prm.policy == DOBFS_POLICY_FORCED_BU ? kDirBU : kDirTD;
