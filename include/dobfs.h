@@ -351,7 +351,7 @@ int dobfs_session_close(dobfs_session_t s);
      level's end (exchanges included), and kernel_ms the host partition's
      time in the level.  Runs of one hybrid graph are serialised.
      Host resources held by the graph: the host rows, `threads - 1` worker
-     threads and 24 ceil(n/64) + 12 min(h, n) + 64 bytes of pinned memory.
+     threads and 24 ceil(n/64) + 8 min(h, n) + 64 bytes of pinned memory.
    dobfs_hybrid_free: releases the graph's device and host memory; NULL is
      accepted.  The caller ensures no run of the graph is in flight.
    Errors: EINVAL (NULL pointers, bad CSR, threads outside [1, 1024], a

@@ -263,6 +263,18 @@ __global__ void __launch_bounds__(kBlock) k_hyb_init(HybGpu p, int64_t root) {
   }
 }
 
+/* Parents of the host partition, read in place from its pinned host array:
+   a hub first reached through a GPU mark (kPending there) keeps the marking
+   GPU vertex that the device recorded in its own parent entry; every other
+   hub takes the host's parent. */
+__global__ void __launch_bounds__(kBlock) k_hyb_merge(int32_t* parent, const int32_t* par_host, int64_t hv) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < hv; v += nth) {
+    const int32_t ph = par_host[v];
+    if (ph != kPending) parent[v] = ph;
+  }
+}
+
 /* Results in caller IDs: entry x takes its internal vertex's depth and the
    caller ID of its parent. */
 __global__ void __launch_bounds__(kBlock) k_hyb_out(const int32_t* depth_i, const int32_t* parent_i,
@@ -412,10 +424,11 @@ struct dobfs_hybrid_s {
   /* pinned host buffers: the whole frontier, the GPU's marks for the host
      and the host's marks for the GPU (W words each), the GPU's counters of
      a level and of its apply step; the host partition's depths and parents
-     and the GPU's first-mark parents of host vertices (max(hv, 1) each) */
+     (max(hv, 1) each; the parents are also read in place by the device) */
   uint64_t *cur_x = nullptr, *gmarks_x = nullptr, *hmarks_x = nullptr;
   unsigned long long* cnt_x = nullptr;
-  int32_t *dep_h = nullptr, *par_h = nullptr, *pm_h = nullptr;
+  int32_t *dep_h = nullptr, *par_h = nullptr;
+  const int32_t* par_h_dev = nullptr;  /* par_h as the device addresses it */
   hipEvent_t ev[2] = {nullptr, nullptr};
   std::mutex mu;
 };
@@ -446,7 +459,7 @@ void release(dobfs_hybrid_s* H) {
                   (void*)H->old2new_g, (void*)H->new2old_g})
     if (p) (void)hipFree(p);
   for (void* p : {(void*)H->cur_x, (void*)H->gmarks_x, (void*)H->hmarks_x, (void*)H->cnt_x, (void*)H->dep_h,
-                  (void*)H->par_h, (void*)H->pm_h})
+                  (void*)H->par_h})
     if (p) (void)hipHostFree(p);
   for (hipEvent_t e : H->ev)
     if (e) (void)hipEventDestroy(e);
@@ -802,11 +815,15 @@ int dobfs_hybrid_upload(const int64_t* offsets, const int32_t* indices, int64_t 
       (e = hipHostMalloc(&H->cnt_x, sizeof(unsigned long long) * 8, hipHostMallocDefault)) != hipSuccess ||
       (e = hipHostMalloc(&H->dep_h, sizeof(int32_t) * (size_t)std::max<int64_t>(hv, 1), hipHostMallocDefault)) !=
           hipSuccess ||
-      (e = hipHostMalloc(&H->par_h, sizeof(int32_t) * (size_t)std::max<int64_t>(hv, 1), hipHostMallocDefault)) !=
-          hipSuccess ||
-      (e = hipHostMalloc(&H->pm_h, sizeof(int32_t) * (size_t)std::max<int64_t>(hv, 1), hipHostMallocDefault)) !=
+      (e = hipHostMalloc(&H->par_h, sizeof(int32_t) * (size_t)std::max<int64_t>(hv, 1), hipHostMallocMapped)) !=
           hipSuccess)
     return undo(hfail(DOBFS_ENOMEM, "pinned exchange buffers", e));
+  {
+    void* dp = nullptr;
+    if ((e = hipHostGetDevicePointer(&dp, H->par_h, 0)) != hipSuccess)
+      return undo(hfail(DOBFS_EDEVICE, "device address of the host parents", e));
+    H->par_h_dev = static_cast<const int32_t*>(dp);
+  }
   if ((e = hipEventCreate(&H->ev[0])) != hipSuccess || (e = hipEventCreate(&H->ev[1])) != hipSuccess)
     return undo(hfail(DOBFS_EDEVICE, "event creation", e));
   if ((e = hipMemcpyAsync(H->off_g, off_i.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, s)) !=
@@ -1044,35 +1061,25 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
   /* deferred parents (Section 3.1), collected after the traversal: the
      GPU partition finds its own in its rows against both partitions'
      depths; a host vertex first reached through a GPU mark takes the GPU
-     vertex whose mark first reached it, recorded on the device */
-  if (hv > 0) {
-    HYB_HIP(hipMemcpyAsync(H->pm_h, H->parent_g, sizeof(int32_t) * (size_t)hv, hipMemcpyDeviceToHost, s),
-            "parent copy");
+     vertex whose mark first reached it, which the device recorded */
+  if (hv > 0)
     HYB_HIP(hipMemcpyAsync(H->depth_g, H->dep_h, sizeof(int32_t) * (size_t)hv, hipMemcpyHostToDevice, s),
             "depth copy");
-  }
   if (timed) HYB_HIP(hipEventRecord(H->ev[0], s), "event");
   hipLaunchKernelGGL(k_hyb_resolve, dim3(grid), dim3(kBlock), 0, s, g, (const int32_t*)H->depth_g);
   HYB_HIP(hipGetLastError(), "resolve launch");
-  if (timed) HYB_HIP(hipEventRecord(H->ev[1], s), "event");
-  HYB_HIP(hipStreamSynchronize(s), "parent copy");
-  if (timed) HYB_HIP(kernel_ms(&aux_ms), "event time");
   if (hv > 0) {
-    pool.run([&](int t) {
-      int64_t lo, hi;
-      share(hv, t, T, &lo, &hi);
-      for (int64_t v = lo; v < hi; ++v)
-        if (H->par_h[v] == kPending) H->par_h[v] = H->pm_h[v];
-    });
-    HYB_HIP(hipMemcpyAsync(H->parent_g, H->par_h, sizeof(int32_t) * (size_t)hv, hipMemcpyHostToDevice, s),
-            "parent copy");
+    hipLaunchKernelGGL(k_hyb_merge, dim3(grid), dim3(kBlock), 0, s, H->parent_g, H->par_h_dev, hv);
+    HYB_HIP(hipGetLastError(), "merge launch");
   }
+  if (timed) HYB_HIP(hipEventRecord(H->ev[1], s), "event");
   /* caller IDs */
   hipLaunchKernelGGL(k_hyb_out, dim3(grid), dim3(kBlock), 0, s, (const int32_t*)H->depth_g,
                      (const int32_t*)H->parent_g, (const int32_t*)H->old2new_g, (const int32_t*)H->new2old_g, n,
                      depth, parent);
   HYB_HIP(hipGetLastError(), "output launch");
   HYB_HIP(hipStreamSynchronize(s), "output");
+  if (timed) HYB_HIP(kernel_ms(&aux_ms), "event time");
   if (stats) {
     stats->levels = levels;
     stats->log_len = std::min(log_len, std::max(stats->log_cap, 0));
