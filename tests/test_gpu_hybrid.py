@@ -200,3 +200,33 @@ def test_hybrid_hub_partition_decides(dobfs):
         with pytest.raises(dobfs.DobfsError) as ei:
             hg.run(int(roots[0]), params=dobfs.make_params("edge", flags=dobfs.RUN_HUB_DECIDES))
         assert ei.value.status == dobfs.EINVAL
+
+
+def test_hybrid_scale24_bench_shape(dobfs):
+    """The hybrid bench's shape at Kronecker scale 24: the rows of the top
+    12% of non-isolated vertices on the host, 16 host threads, EDGE with
+    alpha 56.  Every one of the bench's 16 roots: depths equal to the
+    resident traversal's (itself pinned to the oracle by the parity tests),
+    parents a valid BFS tree by the tree properties, m_c equal."""
+    import torch
+    import bench
+    from tree_props import bfs_tree_violations
+    dg = gg.kronecker_device(24, 16, seed=2)
+    roots = gg.sample_roots_device(dg, 16, seed=1_000_002)
+    host = dg.to_host()
+    off_t, idx_t = dg.offsets_tensor(), dg.indices_tensor()
+    budget, _ = bench.hybrid_budget(host.degrees(), 0.12)
+    params = dobfs.make_params("edge", alpha=56)
+    with dobfs.HybridGraph.upload(host.offsets, host.indices, gpu_budget_bytes=budget, threads=16) as hg, \
+            dobfs.Graph.upload(host.offsets, host.indices, reindex=True) as rg:
+        for r in roots:
+            r = int(r)
+            _say(f"[hybrid] scale 24 bench shape, root {r}")
+            d, p, st = hg.run(r, params=params, stats=True)
+            rd, _, rst = rg.run(r, stats=True)
+            torch.cuda.synchronize()
+            assert torch.equal(d, rd), r
+            assert st.m_c == rst.m_c and st.reached == rst.reached
+            bad = bfs_tree_violations(off_t, idx_t, d, p, r)
+            assert bad == [], (r, bad)
+    dg.free()
