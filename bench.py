@@ -659,12 +659,22 @@ def bench_hybrid(args) -> dict:
     g = dgen.to_host()
     dgen.free()
     log(f"[hybrid] kronecker scale {scale} built (n={g.n}, m={g.m}) in {time.time() - t0:.1f}s")
-    budget, k = hybrid_budget(g.degrees(), args.hybrid_host_frac)
+    deg = g.degrees()
+    n_ni = int((deg > 0).sum())
+    if args.hybrid_budget_gib > 0:
+        budget, k = int(args.hybrid_budget_gib * (1 << 30)), None
+        placement = f"a fixed device budget of {args.hybrid_budget_gib:g} GiB"
+    else:
+        budget, k = hybrid_budget(deg, args.hybrid_host_frac)
+        placement = (f"rows of the top {args.hybrid_host_frac:.0%} of non-isolated vertices by degree class on the "
+                     "host")
     threads = args.hybrid_threads or min(16, len(os.sched_getaffinity(0)))
     t0 = time.time()
     hg = dobfs.HybridGraph.upload(g.offsets, g.indices, gpu_budget_bytes=budget, threads=threads)
     info = hg.info()
-    log(f"[hybrid] split at {info['split']} ({k} asked): host rows {info['host_entries']} entries, device "
+    gpu_share = (n_ni - min(info["split"], n_ni)) / max(n_ni, 1)  # non-isolated vertices form an ID prefix
+    log(f"[hybrid] split at {info['split']} ({k} asked), {gpu_share:.1%} of the non-isolated vertices on the device: "
+        f"host rows {info['host_entries']} entries, device "
         f"{info['gpu_entries']} entries, {info['gpu_bytes'] / 2**30:.2f} GiB on the device; upload "
         f"{time.time() - t0:.1f}s, {threads} host threads")
     flags = dobfs.RUN_HUB_DECIDES if args.hybrid_hub_decides else 0
@@ -719,14 +729,14 @@ def bench_hybrid(args) -> dict:
             "ms_per_step": round(sum(times) / args.steps, 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "int32", "data": "synthetic",
             "config": {"workload": f"kronecker scale {scale} edgefactor {args.edgefactor} seed {args.seed}, "
-                                   f"rows of the top {args.hybrid_host_frac:.0%} of non-isolated vertices by degree "
-                                   f"class on the host ({threads} threads), the rest on the device; "
+                                   f"{placement} ({threads} host threads), the rest on the device; "
                                    f"{args.roots} roots (seed {args.seed + 1_000_000}), policy {args.policy} "
                                    + (f"with alpha {args.hybrid_alpha}" if args.policy == "edge" else "")
                                    + (", the host partition deciding the switch" if args.hybrid_hub_decides else ""),
                        "n": g.n, "m": g.m, "split": info["split"], "host_entries": info["host_entries"],
                        "gpu_entries": info["gpu_entries"], "gpu_bytes": info["gpu_bytes"],
-                       "device_budget": budget, "levels": levels[:len(roots)]},
+                       "device_budget": budget, "gpu_share_nonisolated": round(gpu_share, 4),
+                       "levels": levels[:len(roots)]},
             "resident_gteps": round(res, 3), "host": host_spec()}
 
 
@@ -791,6 +801,8 @@ def main() -> int:
     ap.add_argument("--hybrid-host-frac", type=float, default=0.12,
                     help="hybrid mode: share of the non-isolated vertices (highest degree first) kept on the host")
     ap.add_argument("--hybrid-threads", type=int, default=0, help="hybrid mode: host threads (0: up to 16)")
+    ap.add_argument("--hybrid-budget-gib", type=float, default=0.0,
+                    help="hybrid mode: a fixed device-memory budget instead of --hybrid-host-frac")
     ap.add_argument("--hybrid-hub-decides", action="store_true",
                     help="hybrid mode: the host partition's own next frontier decides the switch (PAPER policy)")
     ap.add_argument("--hybrid-alpha", type=int, default=56,

@@ -329,7 +329,9 @@ int dobfs_session_close(dobfs_session_t s);
      and splits the internal IDs at h, the smallest multiple of 64 whose
      GPU share fits gpu_budget_bytes of device memory: rows of [h, n) go to
      the device with all per-vertex state, rows of [0, h) (the hubs) stay in
-     host memory and are traversed by `threads` host threads.  A budget at
+     host memory and are traversed by `threads` host threads.  (Beyond the
+     budget the device also holds 4 bytes per device row longer than 2,048
+     entries, a list for their top-down expansion.)  A budget at
      or above the whole graph's share puts every row on the GPU (h = 0); a
      budget that holds the per-vertex state only puts every row on the host.
      The library owns *out; the stream orders the uploads.

@@ -73,7 +73,9 @@ struct HybGpu {
   int32_t* depth;      /* int32[n]: the partition's own entries */
   int32_t* parent;     /* int32[n]: the partition's own entries; entry v < h
                           holds the GPU vertex whose mark first reached v */
-  unsigned long long* cnt; /* found, found_deg, checked, scanned */
+  unsigned long long* cnt; /* found, found_deg, checked, scanned; [4]: entries of lng */
+  int32_t* lng;        /* top-down: frontier vertices whose rows are longer than
+                          kHybLongRow, expanded by the whole grid */
 };
 
 __device__ __forceinline__ void hyb_flush(const HybGpu& p, int64_t found, int64_t found_deg, int64_t checked,
@@ -93,8 +95,10 @@ __device__ __forceinline__ void hyb_flush(const HybGpu& p, int64_t found, int64_
 /* Top-down level on the GPU partition: a wavefront per 64-vertex word of
    the partition.  A frontier vertex with at most kHybLaneRow neighbours is
    expanded by its own lane; longer rows are taken one after another by the
-   whole wavefront, lanes striding the row. */
+   whole wavefront, lanes striding the row; rows longer than kHybLongRow
+   (hubs, when the device holds them) are listed for k_hyb_td_long. */
 constexpr int64_t kHybLaneRow = 16;
+constexpr int64_t kHybLongRow = 2048;
 
 __device__ __forceinline__ void hyb_visit(const HybGpu& p, int32_t L, int32_t u, int32_t v, int64_t& found,
                                           int64_t& found_deg) {
@@ -131,8 +135,10 @@ __global__ void __launch_bounds__(kBlock) k_hyb_td(HybGpu p, int32_t L) {
     if (e - b <= kHybLaneRow) {
       for (int64_t k = b; k < e; ++k) hyb_visit(p, L, (int32_t)u, p.idx[k], found, found_deg);
       checked += e - b;
+    } else if (e - b > kHybLongRow) {
+      p.lng[atomicAdd(&p.cnt[4], 1ull)] = (int32_t)u;
     }
-    uint64_t mm = __ballot(e - b > kHybLaneRow);
+    uint64_t mm = __ballot(e - b > kHybLaneRow && e - b <= kHybLongRow);
     while (mm) {
       const int src = __ffsll((unsigned long long)mm) - 1;
       mm &= mm - 1;
@@ -142,6 +148,24 @@ __global__ void __launch_bounds__(kBlock) k_hyb_td(HybGpu p, int32_t L) {
         hyb_visit(p, L, uu, p.idx[k], found, found_deg);
         ++checked;
       }
+    }
+  }
+  hyb_flush(p, found, found_deg, checked, 0);
+}
+
+/* The long rows a top-down level listed, one after another, each striped
+   over every thread of the grid. */
+__global__ void __launch_bounds__(kBlock) k_hyb_td_long(HybGpu p, int32_t L) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t cnt = (int64_t)p.cnt[4];
+  int64_t found = 0, found_deg = 0, checked = 0;
+  for (int64_t i = 0; i < cnt; ++i) {
+    const int32_t u = p.lng[i];
+    const int64_t b = p.off[u], e = p.off[u + 1];
+    for (int64_t k = b + t; k < e; k += nth) {
+      hyb_visit(p, L, u, p.idx[k], found, found_deg);
+      ++checked;
     }
   }
   hyb_flush(p, found, found_deg, checked, 0);
@@ -420,7 +444,9 @@ struct dobfs_hybrid_s {
   uint64_t *vis_g = nullptr, *cur_g = nullptr, *nxt_g = nullptr, *push_g = nullptr, *pulled_g = nullptr;
   int32_t *depth_g = nullptr, *parent_g = nullptr;
   int32_t *old2new_g = nullptr, *new2old_g = nullptr;
-  unsigned long long* cnt_g = nullptr;
+  unsigned long long* cnt_g = nullptr;  /* 5 counters, see HybGpu::cnt */
+  int32_t* lng_g = nullptr;             /* capacity: the device's rows longer than kHybLongRow */
+  int64_t n_long = 0;
   /* pinned host buffers: the whole frontier, the GPU's marks for the host
      and the host's marks for the GPU (W words each), the GPU's counters of
      a level and of its apply step; the host partition's depths and parents
@@ -456,7 +482,7 @@ uint32_t class_of(int64_t d) {
 void release(dobfs_hybrid_s* H) {
   for (void* p : {(void*)H->off_g, (void*)H->idx_g, (void*)H->vis_g, (void*)H->cur_g, (void*)H->nxt_g,
                   (void*)H->push_g, (void*)H->pulled_g, (void*)H->depth_g, (void*)H->parent_g, (void*)H->cnt_g,
-                  (void*)H->old2new_g, (void*)H->new2old_g})
+                  (void*)H->old2new_g, (void*)H->new2old_g, (void*)H->lng_g})
     if (p) (void)hipFree(p);
   for (void* p : {(void*)H->cur_x, (void*)H->gmarks_x, (void*)H->hmarks_x, (void*)H->cnt_x, (void*)H->dep_h,
                   (void*)H->par_h})
@@ -482,6 +508,7 @@ HybGpu gpu_view(const dobfs_hybrid_s* H) {
   p.depth = H->depth_g;
   p.parent = H->parent_g;
   p.cnt = H->cnt_g;
+  p.lng = H->lng_g;
   return p;
 }
 
@@ -795,6 +822,9 @@ int dobfs_hybrid_upload(const int64_t* offsets, const int32_t* indices, int64_t 
 
   /* GPU partition: every vertex's row slot, the rows of [h, n) filled */
   H->gpu_entries = m - off_i[(size_t)hv];
+  int64_t& n_long = H->n_long;
+  for (int64_t v = hv; v < n; ++v)
+    if (H->deg[(size_t)v] > kHybLongRow) ++n_long;
   for (int64_t v = 0; v <= n; ++v) off_i[(size_t)v] = v < hv ? 0 : off_i[(size_t)v] - H->off_h[(size_t)hv];
   if ((e = hipMalloc(&H->off_g, sizeof(int64_t) * (size_t)(n + 1))) != hipSuccess ||
       (e = hipMalloc(&H->idx_g, sizeof(int32_t) * (size_t)std::max<int64_t>(H->gpu_entries, 1))) != hipSuccess ||
@@ -805,7 +835,8 @@ int dobfs_hybrid_upload(const int64_t* offsets, const int32_t* indices, int64_t 
       (e = hipMalloc(&H->pulled_g, sizeof(uint64_t) * (size_t)W)) != hipSuccess ||
       (e = hipMalloc(&H->depth_g, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
       (e = hipMalloc(&H->parent_g, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
-      (e = hipMalloc(&H->cnt_g, sizeof(unsigned long long) * 4)) != hipSuccess ||
+      (e = hipMalloc(&H->cnt_g, sizeof(unsigned long long) * 5)) != hipSuccess ||
+      (e = hipMalloc(&H->lng_g, sizeof(int32_t) * (size_t)std::max<int64_t>(n_long, 1))) != hipSuccess ||
       (e = hipMalloc(&H->old2new_g, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
       (e = hipMalloc(&H->new2old_g, sizeof(int32_t) * (size_t)n)) != hipSuccess)
     return undo(hfail(e == hipErrorOutOfMemory ? DOBFS_ENOMEM : DOBFS_EDEVICE, "GPU partition allocation", e));
@@ -848,7 +879,8 @@ int dobfs_hybrid_info(dobfs_hybrid_t H, int64_t* split, int64_t* host_entries, i
   if (split) *split = H->hv;
   if (host_entries) *host_entries = (int64_t)H->idx_h.size();
   if (gpu_entries) *gpu_entries = H->gpu_entries;
-  if (gpu_bytes) *gpu_bytes = 8 * (H->n + 1) + 4 * H->gpu_entries + 5 * 8 * W + 16 * H->n + 32;
+  if (gpu_bytes)
+    *gpu_bytes = 8 * (H->n + 1) + 4 * H->gpu_entries + 5 * 8 * W + 16 * H->n + 40 + 4 * std::max<int64_t>(H->n_long, 1);
   return DOBFS_OK;
 }
 
@@ -925,10 +957,14 @@ int dobfs_hybrid_run(dobfs_hybrid_t H, int64_t root, int32_t* depth, int32_t* pa
     /* both partitions run level L at once: the GPU's kernel is enqueued,
        then the host threads take the host's share */
     HYB_HIP(hipMemsetAsync(H->nxt_g + Wh, 0, sizeof(uint64_t) * (size_t)Wg, s), "level reset");
-    HYB_HIP(hipMemsetAsync(H->cnt_g, 0, sizeof(unsigned long long) * 4, s), "level reset");
+    HYB_HIP(hipMemsetAsync(H->cnt_g, 0, sizeof(unsigned long long) * 5, s), "level reset");
     if (timed) HYB_HIP(hipEventRecord(H->ev[0], s), "event");
-    if (dir == kDirTD) hipLaunchKernelGGL(k_hyb_td, dim3(grid), dim3(kBlock), 0, s, g, L);
-    else hipLaunchKernelGGL(k_hyb_bu, dim3(grid), dim3(kBlock), 0, s, g, L);
+    if (dir == kDirTD) {
+      hipLaunchKernelGGL(k_hyb_td, dim3(grid), dim3(kBlock), 0, s, g, L);
+      hipLaunchKernelGGL(k_hyb_td_long, dim3(grid), dim3(kBlock), 0, s, g, L);
+    } else {
+      hipLaunchKernelGGL(k_hyb_bu, dim3(grid), dim3(kBlock), 0, s, g, L);
+    }
     HYB_HIP(hipGetLastError(), "level launch");
     if (timed) HYB_HIP(hipEventRecord(H->ev[1], s), "event");
     HYB_HIP(hipMemcpyAsync(cg, H->cnt_g, sizeof(unsigned long long) * 4, hipMemcpyDeviceToHost, s), "counter copy");

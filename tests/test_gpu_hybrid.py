@@ -95,6 +95,20 @@ def test_hybrid_closed_forms(dobfs):
                 label=g.name)
 
 
+def test_hybrid_long_device_rows(dobfs):
+    """Rows longer than 2,048 entries on the device (the whole budget, or
+    half of it) go through the grid-wide top-down expansion: a star whose
+    centre has 19,999 neighbours, and Kronecker scale 16 with every row on
+    the device."""
+    g = gg.star(20000)
+    _parity(dobfs, g, [0, 1, 19999], _budgets(dobfs, g, (0.0, 0.5, 1.0)), policies=("td", "edge", "bu"),
+            label="star20000")
+    g = gg.kronecker(16, seed=13)
+    assert int(g.degrees().max()) > 2048
+    _parity(dobfs, g, gg.sample_roots(g, 3, seed=2), _budgets(dobfs, g, (1.0,)), policies=("td", "edge"),
+            label="kron16/all-device")
+
+
 def test_hybrid_many_levels_and_tails(dobfs):
     g = gg.chung_lu(30000, gamma=2.2, avg_deg=8.0, max_deg=3000.0, n_tails=5, tail_len=150, seed=3)
     roots = gg.sample_roots(g, 2, seed=4)
