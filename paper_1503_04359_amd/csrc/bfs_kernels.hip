@@ -416,109 +416,123 @@ __device__ void bottom_up(const GView& g, const WView& w, const KParams& kp, int
   for (int i = threadIdx.x; i < kBuHot32; i += blockDim.x) hot[i] = i < 2 * W ? f32[i] : 0u;
   __syncthreads();
 
+  /* A wavefront's word groups are wb = (wave + j * nwaves) * K, j = 0, 1, ...
+     Both passes take G of them per step, one word per lane (lane = g * K + k:
+     word k of the step's group g), so a level with most vertices already
+     visited costs one load and one store per lane for G groups instead of a
+     step per group. */
+  constexpr int G = kWave / K;
+  static_assert(kWave % K == 0, "a wavefront holds whole word groups");
+  /* the lane's word is the step's first word (wave-uniform) plus my_off */
+  const uint32_t my_off = (uint32_t)((lane / K) * nwaves * K + (lane % K));
+
   /* ---- pass 1: round 0 ---- */
-  /* the next group's visited words are loaded one iteration ahead; the
-     load is unconditional (an idle lane reads an in-bounds word) and its
-     value is masked only when used, so nothing waits for it early */
-  bool ok_next = lane < K && wave * K + lane < W;
-  uint64_t raw_next = w.vis[ok_next ? wave * K + lane : 0];
-  for (int64_t wb = wave * K; wb < W; wb += nwaves * K) {
-    const uint64_t vis_mine = ok_next ? raw_next : ~0ull;  /* lanes 0..K-1: word wb+lane */
-    {
-      const int64_t nx = wb + nwaves * K + lane;
-      ok_next = lane < K && nx < W;
-      raw_next = w.vis[ok_next ? nx : wb];
+  for (int64_t j0 = 0; (wave + j0 * nwaves) * K < W; j0 += G) {
+    const int64_t sb = (wave + j0 * nwaves) * K;
+    const bool my_ok = (int64_t)my_off < W - sb;
+    const uint64_t my_vis = my_ok ? w.vis[sb + my_off] : ~0ull;
+    const uint64_t busy = __ballot(my_vis != ~0ull);
+    /* every vertex of the lane's group visited: nothing reached, nothing to search */
+    if (my_ok && !((busy >> (lane & ~(K - 1))) & ((1ull << K) - 1ull))) {
+      (f_nxt + sb)[my_off] = 0ull;
+      (rec + 2 * sb)[2 * my_off + 1] = 0ull;
     }
-    if (!__ballot(lane < K && vis_mine != ~0ull)) {
+    uint64_t todo = busy;
+    while (todo) {
+      const int gsel = (__ffsll((unsigned long long)todo) - 1) / K;
+      todo &= ~(((1ull << K) - 1ull) << (gsel * K));
+      const int64_t wb = (wave + (j0 + gsel) * nwaves) * K;
+      /* lanes 0..K-1: word wb+lane (~0 past the end) */
+      const uint64_t vis_mine = __shfl(my_vis, gsel * K + (lane & (K - 1)));
+      /* Every load is issued before any is used, and none sits under a
+         branch (lanes with nothing to load read entry 0 of the word group,
+         which is in bounds), so the compiler can wait for each one alone
+         instead of for everything outstanding.  Addresses are a wave-uniform
+         base plus a 32-bit lane offset. */
+      const int64_t v0 = wb * kWave;
+      const uint32_t* off_lo = reinterpret_cast<const uint32_t*>(g.off + v0);
+      const int32_t* first = g.first + v0;
+      uint32_t b[K], e[K], fw[K];
+      int32_t u0[K], pcr[K];
+      bool unv[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint64_t vw = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(vis_mine >> 32), k) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)vis_mine, k);
+        unv[k] = ((vw >> lane) & 1ull) == 0ull;  /* bits >= n are set */
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = unv[k] ? k * kWave + lane : 0;
+        /* degrees fit in 31 bits, so the low words of the row bounds give
+           the degree */
+        b[k] = off_lo[2 * i];
+        e[k] = off_lo[2 * i + 2];
+        u0[k] = first[i];
+        /* the first neighbour's caller ID, in case it is the parent: loaded
+           with the rest rather than after the frontier test */
+        pcr[k] = g.first_caller ? g.first_caller[v0 + i] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (!unv[k]) e[k] = b[k];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t u = e[k] != b[k] ? (uint32_t)u0[k] : 0u;
+        fw[k] = frontier_word(hot, f32, u);
+      }
+      uint32_t hit = 0u;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int32_t deg = (int32_t)(e[k] - b[k]);
+        if (deg > 0 && ((fw[k] >> (u0[k] & 31)) & 1u)) hit |= 1u << k;
+        n_scanned += unv[k] ? 1 : 0;
+        n_checked += deg > 0 ? 1 : 0;
+      }
+      uint64_t my_hit = 0ull, my_srch = 0ull;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int32_t deg = (int32_t)(e[k] - b[k]);
+        const bool h = (hit >> k) & 1u;
+        if (h) {
+          store_labels(w, (int32_t)(v0 + k * kWave + lane), L + 1, u0[k], pcr[k]);
+          a.found_deg += deg;
+          n_found += 1;
+        }
+        const uint64_t hm = __ballot(h), sm = __ballot(!h && deg > 1);
+        if (lane == k) {
+          my_hit = hm;
+          my_srch = sm;
+        }
+      }
       if (lane < K && wb + lane < W) {
-        f_nxt[wb + lane] = 0ull;
-        rec[2 * (wb + lane) + 1] = 0ull;
-      }
-      continue;
-    }
-    /* Every load is issued before any is used, and none sits under a
-       branch (lanes with nothing to load read entry 0 of the word group,
-       which is in bounds), so the compiler can wait for each one alone
-       instead of for everything outstanding.  Addresses are a wave-uniform
-       base plus a 32-bit lane offset. */
-    const int64_t v0 = wb * kWave;
-    const uint32_t* off_lo = reinterpret_cast<const uint32_t*>(g.off + v0);
-    const int32_t* first = g.first + v0;
-    uint32_t b[K], e[K], fw[K];
-    int32_t u0[K], pcr[K];
-    bool unv[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const uint64_t vw = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(vis_mine >> 32), k) << 32) |
-                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)vis_mine, k);
-      unv[k] = ((vw >> lane) & 1ull) == 0ull;  /* bits >= n are set */
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = unv[k] ? k * kWave + lane : 0;
-      /* degrees fit in 31 bits, so the low words of the row bounds give
-         the degree */
-      b[k] = off_lo[2 * i];
-      e[k] = off_lo[2 * i + 2];
-      u0[k] = first[i];
-      /* the first neighbour's caller ID, in case it is the parent: loaded
-         with the rest rather than after the frontier test */
-      pcr[k] = g.first_caller ? g.first_caller[v0 + i] : -1;
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (!unv[k]) e[k] = b[k];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const uint32_t u = e[k] != b[k] ? (uint32_t)u0[k] : 0u;
-      fw[k] = frontier_word(hot, f32, u);
-    }
-    uint32_t hit = 0u;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int32_t deg = (int32_t)(e[k] - b[k]);
-      if (deg > 0 && ((fw[k] >> (u0[k] & 31)) & 1u)) hit |= 1u << k;
-      n_scanned += unv[k] ? 1 : 0;
-      n_checked += deg > 0 ? 1 : 0;
-    }
-    uint64_t my_hit = 0ull, my_srch = 0ull;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int32_t deg = (int32_t)(e[k] - b[k]);
-      const bool h = (hit >> k) & 1u;
-      if (h) {
-        store_labels(w, (int32_t)(v0 + k * kWave + lane), L + 1, u0[k], pcr[k]);
-        a.found_deg += deg;
-        n_found += 1;
-      }
-      const uint64_t hm = __ballot(h), sm = __ballot(!h && deg > 1);
-      if (lane == k) {
-        my_hit = hm;
-        my_srch = sm;
-      }
-    }
-    if (lane < K && wb + lane < W) {
-      const int64_t wd = wb + lane;
-      rec[2 * wd + 1] = my_srch;
-      if (my_srch) {
-        rec[2 * wd] = my_hit;  /* finished in pass 2 */
-      } else {
-        f_nxt[wd] = my_hit;
-        if (my_hit) w.vis[wd] = vis_mine | my_hit;
+        const int64_t wd = wb + lane;
+        rec[2 * wd + 1] = my_srch;
+        if (my_srch) {
+          rec[2 * wd] = my_hit;  /* finished in pass 2 */
+        } else {
+          f_nxt[wd] = my_hit;
+          if (my_hit) w.vis[wd] = vis_mine | my_hit;
+        }
       }
     }
   }
+  /* pass 2 reads what other lanes of this wavefront stored in pass 1 */
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
   /* ---- pass 2: later rounds of the recorded words ---- */
-  for (int64_t wb = wave * K; wb < W; wb += nwaves * K) {
-    const uint64_t srch_mine = (lane < K && wb + lane < W) ? rec[2 * (wb + lane) + 1] : 0ull;
-    if (!__ballot(srch_mine != 0ull)) continue;
+  for (int64_t j0 = 0; (wave + j0 * nwaves) * K < W; j0 += G) {
+    const int64_t sb = (wave + j0 * nwaves) * K;
+    const uint64_t my_srch = (int64_t)my_off < W - sb ? (rec + 2 * sb)[2 * my_off + 1] : 0ull;
+    uint64_t todo = __ballot(my_srch != 0ull);
 #pragma unroll 1
-    for (int k = 0; k < K; ++k) {
-      const uint64_t sm = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(srch_mine >> 32), k) << 32) |
-                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)srch_mine, k);
-      if (!sm) continue;
-      const int64_t wd = wb + k;
+    while (todo) {
+      const int li = __ffsll((unsigned long long)todo) - 1;
+      todo &= todo - 1ull;
+      const uint64_t sm = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(my_srch >> 32), li) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)my_srch, li);
+      const int64_t wd = (wave + (j0 + li / K) * nwaves) * K + (li % K);
       const int32_t v = (int32_t)(wd * kWave + lane);
       const bool s = (sm >> lane) & 1ull;
       int64_t pos = 0, end = 0;
