@@ -117,6 +117,35 @@ def test_kronecker_s16_sixteen_roots(dobfs):
     _parity(dobfs, g, roots, label="kron16")
 
 
+def test_kronecker_s22_several_word_groups_per_step(dobfs):
+    """Kronecker scale 22 (2.4M non-isolated vertices): more 64-vertex
+    words than the bottom-up grid's wavefronts take in one step of four
+    words each, so wavefronts hold two word groups per step, with and
+    without the degree relabel.  Depths bit-exact, trees valid, and the
+    per-level counters equal the oracle's replay."""
+    g = gg.kronecker(22, seed=3)
+    roots = [int(r) for r in gg.sample_roots(g, 2, seed=5)]
+    exp = {r: oracle.bfs(g.offsets, g.indices, r)[0] for r in roots}
+    r_off, r_idx, new2old, _ = degree_relabel(g)
+    for reindex in (False, True):
+        with dobfs.Graph.upload(g.offsets, g.indices, reindex=reindex) as dg:
+            for pol in ("edge", "bu"):
+                for r in roots:
+                    _say(f"[parity] kron22/{pol}/reindex={reindex} root={r}")
+                    d, p, st = _run(dobfs, dg, r, params=dobfs.make_params(pol))
+                    assert np.array_equal(d, exp[r]), (pol, reindex, r, np.flatnonzero(d != exp[r])[:10])
+                    code, bad = oracle.check_tree(g.offsets, g.indices, r, d, p)
+                    assert code == 0, (oracle.CHECK_CODES[code], bad)
+                    assert len(st.log) == st.levels
+                    if reindex:
+                        rep = oracle.replay(r_off, r_idx, exp[r][new2old], st.dirs())
+                    else:
+                        rep = oracle.replay(g.offsets, g.indices, exp[r], st.dirs())
+                    got = np.array([[rec["n_f"], rec["m_f"], rec["scanned"], rec["checked"], rec["found"],
+                                     rec["found_deg"]] for rec in st.log])
+                    assert np.array_equal(got, rep[:, :6]), (pol, reindex, r, got, rep[:, :6])
+
+
 @pytest.mark.parametrize("policy", ["td", "bu", "paper", "edge"])
 def test_policy_invariance_kronecker(dobfs, policy):
     g = gg.kronecker(14, seed=3)
