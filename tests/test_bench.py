@@ -77,6 +77,17 @@ def test_level_bytes_and_conversions():
     assert bench.to_queue_bytes([td, bu], 1, 4) == 0.0
 
 
+def test_committed_traffic_matches_the_kernel_sources():
+    """The HBM traffic in profiles/ was counted on the traversal kernels as
+    they stand: its source digest equals the sources' (else the bench line
+    would carry no traffic figure)."""
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+        tr = json.load(f)
+    ent = tr["kron-s30-ef16-seed2/edge/reindex-on"]
+    assert ent["source_sha256"] == bench.kernel_source_digest()
+    assert ent["kernels"]["k_level_bu"]["bytes_per_launch"] > 0
+
+
 def test_host_spec():
     spec = bench.host_spec()
     assert spec["nproc"] >= 1 and spec["cpus_allowed"] >= 1
